@@ -1,0 +1,249 @@
+/*
+ * fastmusic.h -- C ABI of the MI355X (gfx950) fast-MUSIC angle-of-arrival path.
+ *
+ * Paper: B. Li, S. Wang, J. Zhang, X. Cao, C. Zhao, "Ultra-Fast Accurate AoA
+ * Estimation via Automotive Massive-MIMO Radar", arXiv:1911.07434.
+ *
+ * The path has four stages, each one entry point:
+ *   fm_covariance        R = X X^H / T                    eqs. (2)-(3)
+ *   fm_subspace_sample   Method 1: column sampling        Alg. 1, eqs. (8)-(9)
+ *   fm_subspace_project  Method 2: projection + power it. Alg. 2, eq. (11)
+ *   fm_pseudospectrum    P(theta) = 1/(||a||^2-||U^H a||^2) eqs. (5), (10)
+ *   fm_peaks             K largest local maxima of P      eq. (6)
+ * plus a batched form (fm_plan_*) that runs many frames of different shapes
+ * through the same kernels, one launch per stage.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers.  Every array argument is a DEVICE pointer unless stated otherwise;
+ *   the caller allocates and owns it.  The library never frees caller memory.
+ * Complex.   complex64 = interleaved (re, im) float pairs; complex128 =
+ *   interleaved (re, im) double pairs.
+ * Streams.   `stream` is a hipStream_t passed as void* (NULL = the null
+ *   stream).  Every call only enqueues work on that stream and returns; no
+ *   call synchronises.  Outputs are valid once the stream's work completes.
+ * Workspace. Scratch memory comes from the context's arena, sized at
+ *   fm_create; single-frame calls that need more than the arena return
+ *   FM_E_WORKSPACE without launching.  Plans own their own workspace,
+ *   allocated once in fm_plan_create.  Hot-path calls never allocate.
+ * Errors.    Argument, launch and workspace errors are returned synchronously
+ *   as fm_status with a message in fm_last_error; nothing is launched when an
+ *   argument is rejected.  Numerical conditions that can only be seen on the
+ *   device are OR-ed into a per-frame uint32 status word (FM_ST_* bits).
+ * Threads.   A context is used by one host thread at a time.  Calls that
+ *   overlap on the same context from different streams are allowed only for
+ *   entry points that use no arena workspace (fm_covariance, fm_peaks) or
+ *   for plans (each plan owns its workspace).
+ * Determinism. The same inputs give bitwise identical outputs whether a frame
+ *   runs alone or inside a plan with other frames.
+ * Steering.  a_m(theta) = exp(-j*pi*m*sin(theta)), m = 0..M-1 (half-wavelength
+ *   ULA, Sec. II-B; the sign chosen so that a source at +theta peaks at
+ *   +theta).  Grid theta_l = theta0_deg + l*dtheta_deg, l = 0..L-1.
+ */
+#ifndef FASTMUSIC_H
+#define FASTMUSIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fm_ctx fm_ctx;
+typedef struct fm_plan fm_plan;
+
+typedef enum {
+  FM_OK = 0,
+  FM_E_ARG = 1,          /* invalid argument; nothing launched */
+  FM_E_HIP = 2,          /* HIP runtime error (message in fm_last_error) */
+  FM_E_WORKSPACE = 3,    /* arena too small for this call */
+  FM_E_UNSUPPORTED = 4   /* valid but not supported by this build */
+} fm_status;
+
+/* Operand precision of the large contractions (covariance, sketch products,
+ * steering projection).  Accumulation is FP32 in every mode; the small dense
+ * steps (orthonormalisation, eigen-solves, peak-region denominators) are FP64
+ * in every mode. */
+typedef enum {
+  FM_FP32 = 0,   /* FP32 operands on FP32 MFMA */
+  FM_BF16 = 1,   /* BF16 operands on BF16 MFMA */
+  FM_FP16 = 2    /* FP16 operands on FP16 MFMA */
+} fm_prec;
+
+/* Subspace method of a frame in a plan. */
+typedef enum {
+  FM_METHOD_PROJECT = 0, /* Method 2, Alg. 2 */
+  FM_METHOD_SAMPLE = 1   /* Method 1, Alg. 1 */
+} fm_method;
+
+/* per-frame device status bits */
+#define FM_ST_NONFINITE      1u  /* NaN/Inf met in an input or intermediate */
+#define FM_ST_EIG_MAXIT      4u  /* a Jacobi eigen-solve hit its sweep limit */
+#define FM_ST_RANK_DEFICIENT 8u  /* fewer than K non-zero directions survived */
+#define FM_ST_FEW_PEAKS     16u  /* fewer than K local maxima */
+#define FM_ST_BAD_INDEX     32u  /* sampled index outside [0, M) or repeated */
+
+/* Default relative threshold of the eigen-based pseudo-inverse, eq. (8):
+ * eigenvalues lambda <= rcond * lambda_max of the p x p (or l x l) core are
+ * dropped. */
+#define FM_RCOND_DEFAULT 1e-6
+
+/* ------------------------------------------------------------------------ */
+/* context                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` with a device arena of
+ * `workspace_bytes` for single-frame calls (0 = a default of 64 MiB).
+ * *out receives the context; on failure *out is NULL. */
+fm_status fm_create(int device, size_t workspace_bytes, fm_ctx **out);
+
+/* Release the context and its arena (waits for the device to go idle). */
+fm_status fm_destroy(fm_ctx *ctx);
+
+/* Static text of a status code. */
+const char *fm_status_string(fm_status s);
+
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char *fm_last_error(const fm_ctx *ctx);
+
+/* Arena bytes one single-frame call sequence needs for an M-channel frame
+ * with sketch width n (l for Method 2, p for Method 1), K sources. */
+size_t fm_workspace_bytes(int M, int n, int K);
+
+/* ------------------------------------------------------------------------ */
+/* stage 1: covariance, eqs. (2)-(3)                                        */
+/* ------------------------------------------------------------------------ */
+
+/* R = X X^H / T.
+ *   X   complex64 [M][ldx], row m = channel m, column t = snapshot t (ldx >= T)
+ *   R   complex64 [M][ldr] (ldr >= M); every entry is written; R is exactly
+ *       Hermitian (R[j][i] == conj(R[i][j]) bit for bit, imaginary diagonal 0)
+ *   prec operand precision (accumulation FP32; the 1/T scale is applied in
+ *       FP32 after accumulation)
+ * Requires M >= 1, T >= 1.  No workspace. */
+fm_status fm_covariance(fm_ctx *ctx, void *stream, const void *X, int M, int T,
+                        int64_t ldx, void *R, int64_t ldr, fm_prec prec);
+
+/* ------------------------------------------------------------------------ */
+/* stage 2a: Method 1 -- uniform column sampling + Nystrom, Alg. 1           */
+/* ------------------------------------------------------------------------ */
+
+/* Signal subspace of S~ = C W C^H with C = R(:, I) and W = pinv(R(I, I))
+ * (eqs. (8)-(9)), restricted to its K leading eigen-directions (Alg. 1 step 2).
+ *   R      complex64 [M][ldr], Hermitian (rows idx are read)
+ *   idx    int32 [p] distinct indices in [0, M) (device)
+ *   rcond  pseudo-inverse threshold (FM_RCOND_DEFAULT)
+ *   Us     complex128 [K][M]: column k of U_s stored contiguously, ordered by
+ *          decreasing sigma.  Column phases are arbitrary: the contract is the
+ *          projector U_s U_s^H.
+ *   sigma  double [K]: leading eigenvalues of S~ (descending)
+ *   status uint32 [1] (device): FM_ST_* bits of this frame (overwritten)
+ * Requires 1 <= K <= p <= M.  Uses workspace. */
+fm_status fm_subspace_sample(fm_ctx *ctx, void *stream, const void *R, int M, int64_t ldr,
+                             const int32_t *idx, int p, int K, double rcond,
+                             void *Us, double *sigma, uint32_t *status);
+
+/* ------------------------------------------------------------------------ */
+/* stage 2b: Method 2 -- Gaussian projection + power iterations, Alg. 2      */
+/* ------------------------------------------------------------------------ */
+
+/* V = orth(R^q Omega), C = R V, W = pinv(V^H C); U_s = K leading
+ * eigen-directions of S~ = C W C^H (Alg. 2, eq. (11)); q = 0 means
+ * V = orth(Omega).  Exactly q+1 products with R are formed.
+ *   Omega  float32 [M][l], real N(0,1) entries (caller-drawn)
+ *   prec   operand precision of the products with R
+ *   Us, sigma, status as in fm_subspace_sample
+ * Requires 1 <= K <= l <= M, 0 <= q <= 16, l <= 64.  Uses workspace. */
+fm_status fm_subspace_project(fm_ctx *ctx, void *stream, const void *R, int M, int64_t ldr,
+                              const float *Omega, int l, int q, int K, double rcond,
+                              fm_prec prec, void *Us, double *sigma, uint32_t *status);
+
+/* ------------------------------------------------------------------------ */
+/* stage 3: pseudo-spectrum, eqs. (5) and (10)                               */
+/* ------------------------------------------------------------------------ */
+
+/* P_l = 1 / (M - ||U_s^H a(theta_l)||^2) on the grid theta_l.  The bulk of
+ * the grid is evaluated with FP32 (or compensated BF16/FP16) products; every
+ * point whose denominator falls below M/16 -- the cancellation-prone region
+ * around peaks -- is recomputed in FP64.  A denominator below M*2^-53 is
+ * clamped there (the pole of a noiseless on-grid source).
+ *   Us  complex128 [K][M] orthonormal columns (stage 2 output)
+ *   P   float32 [L] (linear scale)
+ * Requires 1 <= K <= 64, K <= M, L >= 1, dtheta_deg > 0.  Uses workspace. */
+fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, int M, int K,
+                            double theta0_deg, double dtheta_deg, int L, fm_prec prec,
+                            float *P);
+
+/* ------------------------------------------------------------------------ */
+/* stage 4: peaks, eq. (6)                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* l is a peak if P[l] > P[l-1] (l > 0) and P[l] >= P[l+1] (l < L-1); a
+ * plateau reports its leftmost point.  The K largest peaks are written in
+ * order of decreasing value, ties to the lower index.
+ *   P        float32 [L]
+ *   idx      int32 [K]   grid indices (angle = theta0 + idx*dtheta)
+ *   val      float32 [K] P at those indices
+ *   n_found  int32 [1]   number of peaks written (<= K)
+ * Requires 1 <= L <= 1048576, 1 <= K <= 64.  No workspace. */
+fm_status fm_peaks(fm_ctx *ctx, void *stream, const float *P, int L, int K,
+                   int32_t *idx, float *val, int32_t *n_found);
+
+/* ------------------------------------------------------------------------ */
+/* batched frames: one launch per stage for many frames                     */
+/* ------------------------------------------------------------------------ */
+
+/* One frame of a plan.  All pointers are device pointers owned by the caller
+ * and must stay valid while the plan is used. */
+typedef struct {
+  const void *X;      /* complex64 [M][ldx] snapshots */
+  int64_t ldx;
+  int M, T;
+  void *R;            /* complex64 [M][ldr] covariance (written by stage 1) */
+  int64_t ldr;
+  int K;              /* number of sources */
+  int method;         /* fm_method */
+  int n;              /* sketch width: l (Method 2) or p (Method 1) */
+  int q;              /* power iterations (Method 2) */
+  double rcond;
+  const float *Omega; /* float32 [M][n] (Method 2) */
+  const int32_t *idx; /* int32 [n] (Method 1) */
+  void *Us;           /* complex128 [K][M] */
+  double *sigma;      /* double [K] */
+  uint32_t *status;   /* uint32 [1] */
+  int L;
+  double theta0_deg, dtheta_deg;
+  float *P;           /* float32 [L] */
+  int32_t *peak_idx;  /* int32 [K] */
+  float *peak_val;    /* float32 [K] */
+  int32_t *n_found;   /* int32 [1] */
+} fm_frame;
+
+/* Build a plan for n_frames frames (host array, copied): validates every
+ * frame, builds the per-stage work lists (longest-first), uploads them and
+ * allocates the plan's workspace.  Synchronises the device once.  Each
+ * frame is computed exactly as the single-frame entry points compute it. */
+fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,
+                         fm_plan **out);
+fm_status fm_plan_destroy(fm_plan *plan);
+
+/* Device bytes the plan allocated for its workspace and work lists. */
+size_t fm_plan_workspace_bytes(const fm_plan *plan);
+
+/* Stages of all frames of the plan, each one kernel launch (stage 2 is a
+ * fixed sequence of launches), enqueued on `stream`. */
+fm_status fm_plan_covariance(fm_plan *plan, void *stream);
+fm_status fm_plan_subspace(fm_plan *plan, void *stream);
+fm_status fm_plan_pseudospectrum(fm_plan *plan, void *stream);
+fm_status fm_plan_peaks(fm_plan *plan, void *stream);
+
+/* All four stages.  With use_graph != 0 the sequence is captured once into a
+ * HIP graph (on the first call for a given stream) and replayed afterwards. */
+fm_status fm_plan_run(fm_plan *plan, void *stream, int use_graph);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTMUSIC_H */

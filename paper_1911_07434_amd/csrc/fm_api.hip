@@ -1,0 +1,668 @@
+// fm_api.hip -- the C ABI of fastmusic.h: argument validation, the context
+// arena, single-frame stage sequences and batched plans.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fm_internal.h"
+
+#define FM_API extern "C" __attribute__((visibility("default")))
+
+using fm::FrameDev;
+using fm::Item;
+
+struct fm_ctx {
+  int device = 0;
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  std::string err;
+};
+
+struct fm_plan {
+  fm_ctx *ctx = nullptr;
+  fm_prec prec = FM_FP32;
+  int n_frames = 0;
+  std::vector<FrameDev> frames_h;
+  FrameDev *frames_d = nullptr;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  Item *items_d = nullptr;
+  size_t items_bytes = 0;
+  // a launch = (kind, mode/class, offset into items_d, count)
+  struct Launch {
+    int kind, mode, n_class;
+    size_t off;
+    int count;
+  };
+  std::vector<Launch> cov, sub, spec, peaks;
+  // the graph is captured once on a private stream (the null stream cannot
+  // be captured) and launched on whichever stream the caller passes
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+enum Kind { kCov, kOmega, kGather, kSketch, kGram, kSmall, kApply, kSpec, kPeaks };
+
+fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+fm_status hip_fail(fm_ctx *ctx, hipError_t e, const char *where) {
+  return fail(ctx, FM_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// per-frame workspace layout (shared by single-frame calls and plans)
+struct WsLayout {
+  size_t y, v, part, small, uf, total;
+};
+
+WsLayout ws_layout(int M, int n, int K) {
+  const int np = (n + 1) & ~1;
+  const int nchunk = (M + fm::kGramRows - 1) / fm::kGramRows;
+  WsLayout w;
+  size_t o = 0;
+  w.y = o;     o += align256((size_t)M * n * 8);
+  w.v = o;     o += align256((size_t)M * n * 8);
+  w.part = o;  o += align256((size_t)nchunk * 2 * n * n * 16);
+  w.small = o; o += align256(((size_t)fm::kSmallSlots * np * np + 1) * 16);
+  w.uf = o;    o += align256((size_t)M * K * 8);
+  w.total = o;
+  return w;
+}
+
+void bind_ws(FrameDev &f, char *base, const WsLayout &w) {
+  f.Y = reinterpret_cast<float2 *>(base + w.y);
+  f.V = reinterpret_cast<float2 *>(base + w.v);
+  f.part = reinterpret_cast<double2 *>(base + w.part);
+  f.small = reinterpret_cast<double2 *>(base + w.small);
+  f.Uf = reinterpret_cast<float2 *>(base + w.uf);
+  f.nchunk = (f.M + fm::kGramRows - 1) / fm::kGramRows;
+  f.npad = (f.n + 1) & ~1;
+}
+
+FrameDev blank_frame() {
+  FrameDev f;
+  std::memset(&f, 0, sizeof f);
+  return f;
+}
+
+bool prec_ok(fm_prec p) { return p == FM_FP32 || p == FM_BF16 || p == FM_FP16; }
+
+fm_status set_dev(fm_ctx *ctx) {
+  hipError_t e = hipSetDevice(ctx->device);
+  return e == hipSuccess ? FM_OK : hip_fail(ctx, e, "hipSetDevice");
+}
+
+#define FM_CHECK_LAUNCH(ctx, call)                                   \
+  do {                                                               \
+    hipError_t _e = (call);                                          \
+    if (_e != hipSuccess) return hip_fail((ctx), _e, #call);         \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// validation shared by single-frame calls and plans
+// ---------------------------------------------------------------------------
+fm_status check_cov(fm_ctx *c, const void *X, int M, int T, int64_t ldx, const void *R,
+                    int64_t ldr) {
+  if (!X || !R) return fail(c, FM_E_ARG, "covariance: null pointer");
+  if (M < 1 || T < 1) return fail(c, FM_E_ARG, "covariance: need M >= 1 and T >= 1 (M=%d T=%d)", M, T);
+  if (ldx < T) return fail(c, FM_E_ARG, "covariance: ldx (%lld) < T (%d)", (long long)ldx, T);
+  if (ldr < M) return fail(c, FM_E_ARG, "covariance: ldr (%lld) < M (%d)", (long long)ldr, M);
+  return FM_OK;
+}
+
+fm_status check_sub(fm_ctx *c, const void *R, int M, int64_t ldr, int method, int n, int q,
+                    int K, double rcond, const void *rnd, const void *Us, const void *sigma,
+                    const void *status) {
+  if (!R || !rnd || !Us || !sigma || !status) return fail(c, FM_E_ARG, "subspace: null pointer");
+  if (M < 2) return fail(c, FM_E_ARG, "subspace: need M >= 2 (M=%d)", M);
+  if (ldr < M) return fail(c, FM_E_ARG, "subspace: ldr (%lld) < M (%d)", (long long)ldr, M);
+  if (K < 1 || K > n || n > M)
+    return fail(c, FM_E_ARG, "subspace: need 1 <= K <= n <= M (K=%d n=%d M=%d)", K, n, M);
+  if (K > fm::kMaxK) return fail(c, FM_E_UNSUPPORTED, "subspace: K=%d > %d", K, fm::kMaxK);
+  if (!(rcond >= 0.0) || !std::isfinite(rcond)) return fail(c, FM_E_ARG, "subspace: bad rcond");
+  if (method == FM_METHOD_PROJECT) {
+    if (n > fm::kMaxL) return fail(c, FM_E_UNSUPPORTED, "subspace_project: l=%d > %d", n, fm::kMaxL);
+    if (q < 0 || q > 16) return fail(c, FM_E_ARG, "subspace_project: need 0 <= q <= 16 (q=%d)", q);
+  } else if (method == FM_METHOD_SAMPLE) {
+    if (n > fm::kMaxN) return fail(c, FM_E_UNSUPPORTED, "subspace_sample: p=%d > %d", n, fm::kMaxN);
+  } else {
+    return fail(c, FM_E_ARG, "subspace: unknown method %d", method);
+  }
+  return FM_OK;
+}
+
+fm_status check_spec(fm_ctx *c, const void *Us, int M, int K, double th0, double dth, int L,
+                     const void *P) {
+  if (!Us || !P) return fail(c, FM_E_ARG, "pseudospectrum: null pointer");
+  if (M < 1 || K < 1 || K > M) return fail(c, FM_E_ARG, "pseudospectrum: need 1 <= K <= M (K=%d M=%d)", K, M);
+  if (K > fm::kMaxK) return fail(c, FM_E_UNSUPPORTED, "pseudospectrum: K=%d > %d", K, fm::kMaxK);
+  if (L < 1) return fail(c, FM_E_ARG, "pseudospectrum: need L >= 1");
+  if (!(dth > 0.0) || !std::isfinite(dth) || !std::isfinite(th0))
+    return fail(c, FM_E_ARG, "pseudospectrum: need finite theta0 and dtheta > 0");
+  return FM_OK;
+}
+
+fm_status check_peaks(fm_ctx *c, const void *P, int L, int K, const void *idx, const void *val,
+                      const void *nf) {
+  if (!P || !idx || !val || !nf) return fail(c, FM_E_ARG, "peaks: null pointer");
+  if (L < 1 || L > (1 << 20)) return fail(c, FM_E_ARG, "peaks: need 1 <= L <= 2^20 (L=%d)", L);
+  if (K < 1 || K > fm::kMaxK) return fail(c, FM_E_ARG, "peaks: need 1 <= K <= %d (K=%d)", fm::kMaxK, K);
+  return FM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single-frame stage-2 sequences (identical kernels to the batched plan)
+// ---------------------------------------------------------------------------
+hipError_t run_project_single(FrameDev &f, hipStream_t s, fm_prec prec) {
+  hipError_t e;
+  auto orth = [&]() -> hipError_t {
+    hipError_t r;
+    if ((r = fm::launch_gram(f, nullptr, nullptr, 0, fm::kGramSelf, s)) != hipSuccess) return r;
+    if ((r = fm::launch_small(f, nullptr, nullptr, 0, fm::kOrth, s)) != hipSuccess) return r;
+    return fm::launch_apply(f, nullptr, nullptr, 0, fm::kApplyV, s);
+  };
+  if ((e = fm::launch_omega(f, nullptr, nullptr, 0, 0, s)) != hipSuccess) return e;
+  if (f.q == 0) {
+    if ((e = orth()) != hipSuccess) return e;
+    if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, prec, s)) != hipSuccess) return e;
+  } else {
+    if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, prec, s)) != hipSuccess) return e;
+    for (int i = 0; i < f.q; ++i) {
+      if ((e = orth()) != hipSuccess) return e;
+      if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, prec, s)) != hipSuccess) return e;
+    }
+  }
+  if ((e = fm::launch_gram(f, nullptr, nullptr, 0, fm::kGramFinal, s)) != hipSuccess) return e;
+  if ((e = fm::launch_small(f, nullptr, nullptr, 0, fm::kFinal, s)) != hipSuccess) return e;
+  return fm::launch_apply(f, nullptr, nullptr, 0, fm::kApplyUs, s);
+}
+
+hipError_t run_sample_single(FrameDev &f, hipStream_t s) {
+  hipError_t e;
+  if ((e = fm::launch_gather(f, nullptr, nullptr, 0, s)) != hipSuccess) return e;
+  if ((e = fm::launch_gram(f, nullptr, nullptr, 0, fm::kGramFinal, s)) != hipSuccess) return e;
+  if ((e = fm::launch_small(f, nullptr, nullptr, 0, fm::kFinal, s)) != hipSuccess) return e;
+  return fm::launch_apply(f, nullptr, nullptr, 0, fm::kApplyUs, s);
+}
+
+int small_class(int n) {
+  if (n <= 16) return 16;
+  if (n <= 32) return 32;
+  if (n <= fm::kSmallLdsN) return fm::kSmallLdsN;
+  return fm::kMaxN;
+}
+
+}  // namespace
+
+// ===========================================================================
+// context
+// ===========================================================================
+
+FM_API const char *fm_status_string(fm_status s) {
+  switch (s) {
+    case FM_OK: return "ok";
+    case FM_E_ARG: return "invalid argument";
+    case FM_E_HIP: return "HIP runtime error";
+    case FM_E_WORKSPACE: return "workspace too small";
+    case FM_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+FM_API const char *fm_last_error(const fm_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+FM_API size_t fm_workspace_bytes(int M, int n, int K) {
+  if (M < 1 || n < 1 || K < 0) return 0;
+  return ws_layout(M, n, K).total;
+}
+
+FM_API fm_status fm_create(int device, size_t workspace_bytes, fm_ctx **out) {
+  if (!out) return FM_E_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FM_E_ARG;
+  fm_ctx *c = new (std::nothrow) fm_ctx;
+  if (!c) return FM_E_WORKSPACE;
+  c->device = device;
+  c->arena_bytes = workspace_bytes ? workspace_bytes : (size_t)64 << 20;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipMalloc((void **)&c->arena, c->arena_bytes) != hipSuccess) {
+    delete c;
+    return FM_E_HIP;
+  }
+  *out = c;
+  return FM_OK;
+}
+
+FM_API fm_status fm_destroy(fm_ctx *ctx) {
+  if (!ctx) return FM_E_ARG;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  if (ctx->arena) hipFree(ctx->arena);
+  delete ctx;
+  return FM_OK;
+}
+
+// ===========================================================================
+// single-frame stages
+// ===========================================================================
+
+FM_API fm_status fm_covariance(fm_ctx *ctx, void *stream, const void *X, int M, int T,
+                               int64_t ldx, void *R, int64_t ldr, fm_prec prec) {
+  if (!ctx) return FM_E_ARG;
+  fm_status st = check_cov(ctx, X, M, T, ldx, R, ldr);
+  if (st != FM_OK) return st;
+  if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "covariance: bad precision %d", (int)prec);
+  if (prec != FM_FP32) return fail(ctx, FM_E_UNSUPPORTED, "covariance: only FM_FP32 in this build");
+  if ((st = set_dev(ctx)) != FM_OK) return st;
+  FrameDev f = blank_frame();
+  f.X = static_cast<const float2 *>(X);
+  f.ldx = ldx;
+  f.M = M;
+  f.T = T;
+  f.R = static_cast<float2 *>(R);
+  f.ldr = ldr;
+  FM_CHECK_LAUNCH(ctx, fm::launch_covariance(f, nullptr, nullptr, 0, prec, (hipStream_t)stream));
+  return FM_OK;
+}
+
+static fm_status subspace_single(fm_ctx *ctx, void *stream, const void *R, int M, int64_t ldr,
+                                 int method, const void *rnd, int n, int q, int K, double rcond,
+                                 fm_prec prec, void *Us, double *sigma, uint32_t *status) {
+  if (!ctx) return FM_E_ARG;
+  fm_status st = check_sub(ctx, R, M, ldr, method, n, q, K, rcond, rnd, Us, sigma, status);
+  if (st != FM_OK) return st;
+  if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "subspace: bad precision %d", (int)prec);
+  if (prec != FM_FP32) return fail(ctx, FM_E_UNSUPPORTED, "subspace: only FM_FP32 in this build");
+  const WsLayout w = ws_layout(M, n, K);
+  if (w.total > ctx->arena_bytes)
+    return fail(ctx, FM_E_WORKSPACE, "subspace: needs %zu arena bytes, have %zu", w.total,
+                ctx->arena_bytes);
+  if ((st = set_dev(ctx)) != FM_OK) return st;
+  FrameDev f = blank_frame();
+  f.R = static_cast<float2 *>(const_cast<void *>(R));
+  f.ldr = ldr;
+  f.M = M;
+  f.K = K;
+  f.method = method;
+  f.n = n;
+  f.q = q;
+  f.rcond = rcond;
+  if (method == FM_METHOD_PROJECT) f.Omega = static_cast<const float *>(rnd);
+  else f.idx = static_cast<const int *>(rnd);
+  f.Us = static_cast<double2 *>(Us);
+  f.sigma = sigma;
+  f.status = status;
+  bind_ws(f, ctx->arena, w);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = method == FM_METHOD_PROJECT ? run_project_single(f, s, prec) : run_sample_single(f, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "subspace launch");
+  return FM_OK;
+}
+
+FM_API fm_status fm_subspace_sample(fm_ctx *ctx, void *stream, const void *R, int M,
+                                    int64_t ldr, const int32_t *idx, int p, int K, double rcond,
+                                    void *Us, double *sigma, uint32_t *status) {
+  return subspace_single(ctx, stream, R, M, ldr, FM_METHOD_SAMPLE, idx, p, 0, K, rcond, FM_FP32,
+                         Us, sigma, status);
+}
+
+FM_API fm_status fm_subspace_project(fm_ctx *ctx, void *stream, const void *R, int M,
+                                     int64_t ldr, const float *Omega, int l, int q, int K,
+                                     double rcond, fm_prec prec, void *Us, double *sigma,
+                                     uint32_t *status) {
+  return subspace_single(ctx, stream, R, M, ldr, FM_METHOD_PROJECT, Omega, l, q, K, rcond, prec,
+                         Us, sigma, status);
+}
+
+FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, int M, int K,
+                                   double theta0_deg, double dtheta_deg, int L, fm_prec prec,
+                                   float *P) {
+  if (!ctx) return FM_E_ARG;
+  fm_status st = check_spec(ctx, Us, M, K, theta0_deg, dtheta_deg, L, P);
+  if (st != FM_OK) return st;
+  if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "pseudospectrum: bad precision %d", (int)prec);
+  if (prec != FM_FP32) return fail(ctx, FM_E_UNSUPPORTED, "pseudospectrum: only FM_FP32 in this build");
+  const size_t need = align256((size_t)M * K * 8);
+  if (need > ctx->arena_bytes)
+    return fail(ctx, FM_E_WORKSPACE, "pseudospectrum: needs %zu arena bytes", need);
+  if ((st = set_dev(ctx)) != FM_OK) return st;
+  FrameDev f = blank_frame();
+  f.M = M;
+  f.K = K;
+  f.Us = static_cast<double2 *>(const_cast<void *>(Us));
+  f.Uf = reinterpret_cast<float2 *>(ctx->arena);
+  f.L = L;
+  f.theta0 = theta0_deg;
+  f.dtheta = dtheta_deg;
+  f.P = P;
+  hipStream_t s = (hipStream_t)stream;
+  FM_CHECK_LAUNCH(ctx, fm::launch_uf(f, s));
+  FM_CHECK_LAUNCH(ctx, fm::launch_spectrum(f, nullptr, nullptr, 0, prec, s));
+  return FM_OK;
+}
+
+FM_API fm_status fm_peaks(fm_ctx *ctx, void *stream, const float *P, int L, int K, int32_t *idx,
+                          float *val, int32_t *n_found) {
+  if (!ctx) return FM_E_ARG;
+  fm_status st = check_peaks(ctx, P, L, K, idx, val, n_found);
+  if (st != FM_OK) return st;
+  if ((st = set_dev(ctx)) != FM_OK) return st;
+  FrameDev f = blank_frame();
+  f.P = const_cast<float *>(P);
+  f.L = L;
+  f.K = K;
+  f.peak_idx = idx;
+  f.peak_val = val;
+  f.n_found = n_found;
+  FM_CHECK_LAUNCH(ctx, fm::launch_peaks(f, nullptr, nullptr, 0, (hipStream_t)stream));
+  return FM_OK;
+}
+
+// ===========================================================================
+// plans
+// ===========================================================================
+
+namespace {
+
+hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
+  if (L.count <= 0) return hipSuccess;
+  const Item *it = p->items_d + L.off;
+  FrameDev cls = blank_frame();
+  cls.n = L.n_class;
+  const FrameDev *fr = p->frames_d;
+  switch (L.kind) {
+    case kCov: return fm::launch_covariance(cls, fr, it, L.count, p->prec, s);
+    case kOmega: return fm::launch_omega(cls, fr, it, L.count, 0, s);
+    case kGather: return fm::launch_gather(cls, fr, it, L.count, s);
+    case kSketch: return fm::launch_sketch(cls, fr, it, L.count, p->prec, s);
+    case kGram: return fm::launch_gram(cls, fr, it, L.count, L.mode, s);
+    case kSmall: return fm::launch_small(cls, fr, it, L.count, L.mode, s);
+    case kApply: return fm::launch_apply(cls, fr, it, L.count, L.mode, s);
+    case kSpec: return fm::launch_spectrum(cls, fr, it, L.count, p->prec, s);
+    case kPeaks: return fm::launch_peaks(cls, fr, it, L.count, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+fm_status run_list(fm_plan *p, const std::vector<fm_plan::Launch> &v, void *stream) {
+  for (const auto &L : v) {
+    hipError_t e = run_launch(p, L, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "plan launch");
+  }
+  return FM_OK;
+}
+
+}  // namespace
+
+FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,
+                                fm_plan **out) {
+  if (!ctx || !out) return FM_E_ARG;
+  *out = nullptr;
+  if (!frames || n_frames < 1) return fail(ctx, FM_E_ARG, "plan: need at least one frame");
+  if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "plan: bad precision %d", (int)prec);
+  if (prec != FM_FP32) return fail(ctx, FM_E_UNSUPPORTED, "plan: only FM_FP32 in this build");
+  for (int i = 0; i < n_frames; ++i) {
+    const fm_frame &a = frames[i];
+    fm_status st = check_cov(ctx, a.X, a.M, a.T, a.ldx, a.R, a.ldr);
+    if (st == FM_OK)
+      st = check_sub(ctx, a.R, a.M, a.ldr, a.method, a.n, a.q, a.K, a.rcond,
+                     a.method == FM_METHOD_PROJECT ? (const void *)a.Omega : (const void *)a.idx,
+                     a.Us, a.sigma, a.status);
+    if (st == FM_OK) st = check_spec(ctx, a.Us, a.M, a.K, a.theta0_deg, a.dtheta_deg, a.L, a.P);
+    if (st == FM_OK) st = check_peaks(ctx, a.P, a.L, a.K, a.peak_idx, a.peak_val, a.n_found);
+    if (st != FM_OK) {
+      std::string m = ctx->err;
+      return fail(ctx, st, "plan frame %d: %s", i, m.c_str());
+    }
+  }
+  fm_status st = set_dev(ctx);
+  if (st != FM_OK) return st;
+  fm_plan *p = new (std::nothrow) fm_plan;
+  if (!p) return fail(ctx, FM_E_WORKSPACE, "plan: out of host memory");
+  p->ctx = ctx;
+  p->prec = prec;
+  p->n_frames = n_frames;
+
+  // workspace: frames packed back to back
+  std::vector<WsLayout> lay(n_frames);
+  std::vector<size_t> off(n_frames);
+  size_t total = 0;
+  for (int i = 0; i < n_frames; ++i) {
+    lay[i] = ws_layout(frames[i].M, frames[i].n, frames[i].K);
+    off[i] = total;
+    total += lay[i].total;
+  }
+  p->ws_bytes = total;
+  hipError_t e = hipMalloc((void **)&p->ws, std::max<size_t>(total, 256));
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(ctx, e, "plan workspace hipMalloc");
+  }
+  p->frames_h.resize(n_frames);
+  for (int i = 0; i < n_frames; ++i) {
+    const fm_frame &a = frames[i];
+    FrameDev f = blank_frame();
+    f.X = static_cast<const float2 *>(a.X);
+    f.ldx = a.ldx;
+    f.M = a.M;
+    f.T = a.T;
+    f.R = static_cast<float2 *>(a.R);
+    f.ldr = a.ldr;
+    f.K = a.K;
+    f.method = a.method;
+    f.n = a.n;
+    f.q = a.q;
+    f.rcond = a.rcond;
+    f.Omega = a.Omega;
+    f.idx = a.idx;
+    f.Us = static_cast<double2 *>(a.Us);
+    f.sigma = a.sigma;
+    f.status = a.status;
+    f.L = a.L;
+    f.theta0 = a.theta0_deg;
+    f.dtheta = a.dtheta_deg;
+    f.P = a.P;
+    f.peak_idx = a.peak_idx;
+    f.peak_val = a.peak_val;
+    f.n_found = a.n_found;
+    bind_ws(f, p->ws + off[i], lay[i]);
+    p->frames_h[i] = f;
+  }
+
+  // ---- work lists -------------------------------------------------------
+  std::vector<Item> items;
+  auto begin = [&]() { return items.size(); };
+  auto add = [&](std::vector<fm_plan::Launch> &v, int kind, int mode, int cls, size_t b) {
+    if (items.size() > b) v.push_back({kind, mode, cls, b, (int)(items.size() - b)});
+  };
+  // longest frames first (by covariance work), so short frames fill the tail
+  std::vector<int> order(n_frames);
+  for (int i = 0; i < n_frames; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const double wa = (double)frames[a].M * frames[a].M * frames[a].T;
+    const double wb = (double)frames[b].M * frames[b].M * frames[b].T;
+    return wa > wb;
+  });
+  auto rows = [](int M, int r) { return (M + r - 1) / r; };
+
+  size_t b0 = begin();
+  for (int i : order) {
+    const int nt = (frames[i].M + fm::kCovTile - 1) / fm::kCovTile;
+    for (int ti = 0; ti < nt; ++ti)
+      for (int tj = 0; tj <= ti; ++tj) items.push_back({i, ti, tj, 0});
+  }
+  add(p->cov, kCov, 0, 0, b0);
+
+  // stage 2 init: Omega -> V / Y (Method 2), gather (Method 1)
+  b0 = begin();
+  for (int i : order)
+    if (frames[i].method == FM_METHOD_PROJECT)
+      for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
+  add(p->sub, kOmega, 0, 0, b0);
+  b0 = begin();
+  for (int i : order)
+    if (frames[i].method == FM_METHOD_SAMPLE)
+      for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
+  add(p->sub, kGather, 0, 0, b0);
+
+  const int classes[4] = {16, 32, fm::kSmallLdsN, fm::kMaxN};
+  auto orth_round = [&](auto pred) {
+    size_t b = begin();
+    for (int i : order)
+      if (pred(i))
+        for (int c = 0; c < rows(frames[i].M, fm::kGramRows); ++c) items.push_back({i, c, 0, 0});
+    add(p->sub, kGram, fm::kGramSelf, 0, b);
+    for (int cl : classes) {
+      b = begin();
+      for (int i : order)
+        if (pred(i) && small_class(frames[i].n) == cl) items.push_back({i, 0, 0, 0});
+      add(p->sub, kSmall, fm::kOrth, cl, b);
+    }
+    b = begin();
+    for (int i : order)
+      if (pred(i))
+        for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
+    add(p->sub, kApply, fm::kApplyV, 0, b);
+  };
+  auto sketch_round = [&](auto pred) {
+    size_t b = begin();
+    for (int i : order)
+      if (pred(i))
+        for (int c = 0; c < rows(frames[i].M, fm::kSketchRows); ++c) items.push_back({i, c, 0, 0});
+    add(p->sub, kSketch, 0, 0, b);
+  };
+  int qmax = 0;
+  for (int i = 0; i < n_frames; ++i)
+    if (frames[i].method == FM_METHOD_PROJECT) qmax = std::max(qmax, frames[i].q);
+  auto is_proj = [&](int i) { return frames[i].method == FM_METHOD_PROJECT; };
+  // round 0: orth(Omega) for q = 0 frames, then the first product for all
+  orth_round([&](int i) { return is_proj(i) && frames[i].q == 0; });
+  sketch_round(is_proj);
+  for (int r = 1; r <= qmax; ++r) {
+    orth_round([&](int i) { return is_proj(i) && frames[i].q >= r; });
+    sketch_round([&](int i) { return is_proj(i) && frames[i].q >= r; });
+  }
+  // final: core and Gram, eigen-solves, U_s
+  b0 = begin();
+  for (int i : order)
+    for (int c = 0; c < rows(frames[i].M, fm::kGramRows); ++c) items.push_back({i, c, 0, 0});
+  add(p->sub, kGram, fm::kGramFinal, 0, b0);
+  for (int cl : classes) {
+    b0 = begin();
+    for (int i : order)
+      if (small_class(frames[i].n) == cl) items.push_back({i, 0, 0, 0});
+    add(p->sub, kSmall, fm::kFinal, cl, b0);
+  }
+  b0 = begin();
+  for (int i : order)
+    for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
+  add(p->sub, kApply, fm::kApplyUs, 0, b0);
+
+  b0 = begin();
+  for (int i : order)
+    for (int t = 0; t < rows(frames[i].L, fm::kSpecAngles); ++t) items.push_back({i, t, 0, 0});
+  add(p->spec, kSpec, 0, 0, b0);
+  b0 = begin();
+  for (int i : order) items.push_back({i, 0, 0, 0});
+  add(p->peaks, kPeaks, 0, 0, b0);
+
+  p->items_bytes = items.size() * sizeof(Item);
+  e = hipMalloc((void **)&p->items_d, std::max<size_t>(p->items_bytes, 256));
+  if (e == hipSuccess) e = hipMalloc((void **)&p->frames_d, sizeof(FrameDev) * n_frames);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->items_d, items.data(), p->items_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->frames_d, p->frames_h.data(), sizeof(FrameDev) * n_frames,
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    fm_plan_destroy(p);
+    return hip_fail(ctx, e, "plan upload");
+  }
+  *out = p;
+  return FM_OK;
+}
+
+FM_API fm_status fm_plan_destroy(fm_plan *p) {
+  if (!p) return FM_E_ARG;
+  hipSetDevice(p->ctx->device);
+  hipDeviceSynchronize();
+  if (p->gexec) hipGraphExecDestroy(p->gexec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  if (p->items_d) hipFree(p->items_d);
+  if (p->frames_d) hipFree(p->frames_d);
+  if (p->ws) hipFree(p->ws);
+  delete p;
+  return FM_OK;
+}
+
+FM_API size_t fm_plan_workspace_bytes(const fm_plan *p) {
+  return p ? p->ws_bytes + p->items_bytes + sizeof(FrameDev) * p->n_frames : 0;
+}
+
+FM_API fm_status fm_plan_covariance(fm_plan *p, void *stream) {
+  return p ? run_list(p, p->cov, stream) : FM_E_ARG;
+}
+FM_API fm_status fm_plan_subspace(fm_plan *p, void *stream) {
+  return p ? run_list(p, p->sub, stream) : FM_E_ARG;
+}
+FM_API fm_status fm_plan_pseudospectrum(fm_plan *p, void *stream) {
+  return p ? run_list(p, p->spec, stream) : FM_E_ARG;
+}
+FM_API fm_status fm_plan_peaks(fm_plan *p, void *stream) {
+  return p ? run_list(p, p->peaks, stream) : FM_E_ARG;
+}
+
+FM_API fm_status fm_plan_run(fm_plan *p, void *stream, int use_graph) {
+  if (!p) return FM_E_ARG;
+  fm_status st = set_dev(p->ctx);
+  if (st != FM_OK) return st;
+  if (!use_graph) {
+    if ((st = run_list(p, p->cov, stream)) != FM_OK) return st;
+    if ((st = run_list(p, p->sub, stream)) != FM_OK) return st;
+    if ((st = run_list(p, p->spec, stream)) != FM_OK) return st;
+    return run_list(p, p->peaks, stream);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (!p->gexec) {
+    hipError_t e = hipSuccess;
+    if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "hipStreamCreateWithFlags");
+    e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "hipStreamBeginCapture");
+    void *cs = (void *)p->cap_stream;
+    fm_status cst = run_list(p, p->cov, cs);
+    if (cst == FM_OK) cst = run_list(p, p->sub, cs);
+    if (cst == FM_OK) cst = run_list(p, p->spec, cs);
+    if (cst == FM_OK) cst = run_list(p, p->peaks, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &g);
+    if (cst != FM_OK) { if (g) hipGraphDestroy(g); return cst; }
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { hipGraphDestroy(g); return hip_fail(p->ctx, e, "hipGraphInstantiate"); }
+    p->graph = g;
+  }
+  hipError_t e = hipGraphLaunch(p->gexec, s);
+  return e == hipSuccess ? FM_OK : hip_fail(p->ctx, e, "hipGraphLaunch");
+}

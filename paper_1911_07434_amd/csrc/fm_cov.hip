@@ -1,0 +1,189 @@
+// fm_cov.hip -- stage 1: sample covariance R = X X^H / T (eqs. (2)-(3)).
+//
+// Complex Hermitian rank-T update on the FP32 matrix cores of gfx950.  The
+// complex product is written as real products (re/im of each snapshot are
+// separate MFMA operands):
+//   Re R_ij = sum_t xr_i xr_j + xi_i xi_j
+//   Im R_ij = sum_t xi_i xr_j - xr_i xi_j
+// so each 32x32 complex block costs four v_mfma_f32_32x32x2_f32 per pair of
+// snapshots.  Only lower-triangle 128x128 tiles are computed; each tile
+// stores R_ij and, mirrored, conj(R_ij) at (j, i), so R is exactly Hermitian
+// and its diagonal exactly real.  Operands stream from global memory straight
+// into MFMA registers (each lane owns a run of 4 consecutive snapshots of one
+// channel), which the FP32 matrix rate leaves ample bandwidth for.
+#include "fm_internal.h"
+
+namespace fm {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ inline void tile_of(int b, int &ti, int &tj) {
+  // b enumerates the lower triangle row by row: (0,0), (1,0), (1,1), (2,0) ...
+  int t = (int)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
+  while ((t + 1) * (t + 2) / 2 <= b) ++t;
+  while (t * (t + 1) / 2 > b) --t;
+  ti = t;
+  tj = b - t * (t + 1) / 2;
+}
+
+// One wave: a 64x64 complex block = 2x2 MFMA blocks of 32x32, each with an
+// accumulator for the real and for the imaginary part.
+struct CovAcc {
+  floatx16 re[2][2];
+  floatx16 im[2][2];
+};
+
+__device__ __forceinline__ void cov_step(CovAcc &acc, const float2 (&a)[2][4],
+                                         const float2 (&b)[2][4]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        acc.re[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bi][s].x, b[bj][s].x,
+                                                              acc.re[bi][bj], 0, 0, 0);
+        acc.im[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bi][s].y, b[bj][s].x,
+                                                              acc.im[bi][bj], 0, 0, 0);
+      }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        acc.re[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bi][s].y, b[bj][s].y,
+                                                              acc.re[bi][bj], 0, 0, 0);
+        acc.im[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[bi][s].x, b[bj][s].y,
+                                                              acc.im[bi][bj], 0, 0, 0);
+      }
+  }
+}
+
+__device__ __forceinline__ void cov_tile(const FrameDev &f, int ti, int tj) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  // the upper 64x64 block of a diagonal tile mirrors the lower one
+  if (ti == tj && wi < wj) return;
+  const int M = f.M, T = f.T;
+  const int r = lane & 31, h = lane >> 5;
+  const int ib = ti * kCovTile + wi * 64;
+  const int jb = tj * kCovTile + wj * 64;
+  // rows past M are clamped to a valid row: they only feed outputs that are
+  // never stored
+  const float2 *pa[2], *pb[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    int ia = min(ib + 32 * q + r, M - 1);
+    int ja = min(jb + 32 * q + r, M - 1);
+    pa[q] = f.X + (size_t)ia * f.ldx + 4 * h;
+    pb[q] = f.X + (size_t)ja * f.ldx + 4 * h;
+  }
+  CovAcc acc;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc.re[bi][bj][v] = 0.f;
+        acc.im[bi][bj][v] = 0.f;
+      }
+
+  const int Tfull = T & ~7;
+  float2 a[2][4], b[2][4];
+  if (Tfull > 0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        a[q][s] = pa[q][s];
+        b[q][s] = pb[q][s];
+      }
+  }
+  for (int t = 0; t < Tfull; t += 8) {
+    float2 an[2][4], bn[2][4];
+    const bool more = (t + 8) < Tfull;
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          an[q][s] = pa[q][t + 8 + s];
+          bn[q][s] = pb[q][t + 8 + s];
+        }
+    }
+    cov_step(acc, a, b);
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          a[q][s] = an[q][s];
+          b[q][s] = bn[q][s];
+        }
+    }
+  }
+  if (Tfull < T) {
+    // ragged tail: snapshots past T contribute zero
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const bool ok = (Tfull + 4 * h + s) < T;
+        a[q][s] = ok ? pa[q][Tfull + s] : make_float2(0.f, 0.f);
+        b[q][s] = ok ? pb[q][Tfull + s] : make_float2(0.f, 0.f);
+      }
+    cov_step(acc, a, b);
+  }
+
+  // epilogue: scale by 1/T after accumulation (correctly rounded divide),
+  // store the lower triangle and its conjugate mirror
+  const float Tf = (float)T;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = ib + 32 * bi + (v >> 2) * 8 + h * 4 + (v & 3);
+        const int j = jb + 32 * bj + r;
+        if (i >= M || j >= M || i < j) continue;
+        const float re = acc.re[bi][bj][v] / Tf;
+        const float im = (i == j) ? 0.f : acc.im[bi][bj][v] / Tf;
+        f.R[(size_t)i * f.ldr + j] = make_float2(re, im);
+        if (i != j) f.R[(size_t)j * f.ldr + i] = make_float2(re, -im);
+      }
+}
+
+template <bool kBatched>
+__global__ __launch_bounds__(256) void cov_fp32_kernel(FrameDev single,
+                                                       const FrameDev *__restrict__ frames,
+                                                       const Item *__restrict__ items) {
+  if constexpr (kBatched) {
+    const Item it = items[blockIdx.x];
+    cov_tile(frames[it.frame], it.a, it.b);
+  } else {
+    int ti, tj;
+    tile_of(blockIdx.x, ti, tj);
+    cov_tile(single, ti, tj);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_covariance(const FrameDev &single, const FrameDev *frames, const Item *items,
+                             int n_items, fm_prec prec, hipStream_t s) {
+  (void)prec;
+  if (items) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(cov_fp32_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames,
+                       items);
+  } else {
+    hipLaunchKernelGGL(cov_fp32_kernel<false>, dim3(cov_tiles(single.M)), dim3(256), 0, s,
+                       single, frames, items);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fm

@@ -1,0 +1,102 @@
+// fm_internal.h -- internal descriptors and launcher declarations of the
+// gfx950 fast-MUSIC library (not installed; the public ABI is fastmusic.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "fastmusic.h"
+
+namespace fm {
+
+// Everything one frame needs on the device: caller buffers (inputs and
+// outputs) plus the frame's slice of workspace.  Batched launches read an
+// array of these; single-frame launches pass one by value.
+struct FrameDev {
+  // stage 1: covariance
+  const float2 *X;
+  long long ldx;
+  int M, T;
+  float2 *R;
+  long long ldr;
+  // stage 2: subspace
+  int K, method, n, q;
+  double rcond;
+  const float *Omega;   // [M][n] real Gaussian (Method 2)
+  const int *idx;       // [n] sampled columns (Method 1)
+  double2 *Us;          // [K][M] complex128
+  double *sigma;        // [K]
+  unsigned *status;     // [1]
+  // stages 3-4: spectrum and peaks
+  int L;
+  double theta0, dtheta;
+  float *P;
+  int *peak_idx;
+  float *peak_val;
+  int *n_found;
+  // workspace (device)
+  float2 *Y;            // [M][n] sketch C (= R V, or gathered columns)
+  float2 *V;            // [M][n] orthonormal basis fed to the next product
+  double2 *part;        // [nchunk][2][n][n] Gram partial sums
+  double2 *small;       // small dense scratch, kSmallSlots * npad^2
+  float2 *Uf;           // [M][K] FP32 copy of U_s for the FP32 spectrum pass
+  int nchunk;           // ceil(M / kGramRows)
+  int npad;             // n rounded up to even
+};
+
+// work item of a batched launch: which frame and which tile of it
+struct Item {
+  int frame, a, b, c;
+};
+
+constexpr int kGramRows = 128;     // rows of the sketch per Gram partial
+constexpr int kSmallSlots = 8;     // npad^2 complex128 matrices per frame
+constexpr int kCovTile = 128;      // covariance tile edge (complex entries)
+constexpr int kSketchRows = 128;   // rows of R per sketch workgroup
+constexpr int kApplyRows = 64;     // rows per apply / gather workgroup
+constexpr int kSpecAngles = 64;    // angles per spectrum workgroup
+constexpr int kMaxL = 64;          // max sketch width of Method 2 (l)
+constexpr int kMaxN = 256;         // max sketch width of Method 1 (p)
+constexpr int kMaxK = 64;          // max number of sources
+constexpr int kSmallLdsN = 64;     // small dense matrices live in LDS up to this n
+
+// small-dense modes
+enum SmallMode { kOrth = 0, kFinal = 1 };
+// gram modes
+// kGramFinal: Method 2 frames get V^H Y (slot 0) and Y^H Y (slot 1), Method 1
+// frames get Y^H Y (slot 1); the method is read from the frame
+enum GramMode { kGramSelf = 0, kGramFinal = 1 };
+// apply modes
+enum ApplyMode { kApplyV = 0, kApplyUs = 1 };
+
+// ---------------------------------------------------------------------------
+// launchers (defined in the .hip files); `single` is used when items == null
+// ---------------------------------------------------------------------------
+hipError_t launch_covariance(const FrameDev &single, const FrameDev *frames,
+                             const Item *items, int n_items, fm_prec prec, hipStream_t s);
+hipError_t launch_omega(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, int to_y, hipStream_t s);
+hipError_t launch_sketch(const FrameDev &single, const FrameDev *frames, const Item *items,
+                         int n_items, fm_prec prec, hipStream_t s);
+hipError_t launch_gather(const FrameDev &single, const FrameDev *frames, const Item *items,
+                         int n_items, hipStream_t s);
+hipError_t launch_gram(const FrameDev &single, const FrameDev *frames, const Item *items,
+                       int n_items, int mode, hipStream_t s);
+hipError_t launch_small(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, int mode, hipStream_t s);
+hipError_t launch_apply(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, int mode, hipStream_t s);
+hipError_t launch_uf(const FrameDev &single, hipStream_t s);
+hipError_t launch_spectrum(const FrameDev &single, const FrameDev *frames, const Item *items,
+                           int n_items, fm_prec prec, hipStream_t s);
+hipError_t launch_peaks(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, hipStream_t s);
+
+// number of workgroups one frame needs in each stage (single-frame grids)
+inline int cov_tiles(int M) {
+  int nt = (M + kCovTile - 1) / kCovTile;
+  return nt * (nt + 1) / 2;
+}
+
+}  // namespace fm

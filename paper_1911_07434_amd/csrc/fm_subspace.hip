@@ -1,0 +1,712 @@
+// fm_subspace.hip -- stage 2: randomized signal subspace (Alg. 1 and Alg. 2).
+//
+// Both methods reduce to: a sketch C (M x n) and a Nystrom core (n x n) with
+// S~ = C core^+ C^H (eqs. (8)-(9)); the K leading eigen-directions of S~ are
+// the signal subspace (rank restriction, Sec. III-A).
+//   Method 1: C = R(:, I), core = R(I, I).
+//   Method 2: C = R V with V = orth(R^q Omega), core = V^H C.
+//
+// The GPU evaluates this without forming S~:
+//   core = E diag(lambda) E^H (Jacobi), P = E_r diag(lambda_r^-1/2)
+//     (eigenvalues lambda <= rcond * lambda_max dropped: the pseudo-inverse)
+//   H = P^H (C^H C) P = W diag(sigma) W^H (Jacobi)
+//   U_s = C P W_K diag(sigma_K^-1/2)
+// which gives the same eigenpairs as S~ = (C P)(C P)^H.  orth() uses the same
+// eigen route on the Gram Y^H Y: V = Y E diag(lambda^-1/2).
+//
+// Kernels (one launch covers every frame of a plan):
+//   omega   Omega (real) -> complex V or Y
+//   sketch  Y = R V on FP32 MFMA (R streamed once per product)
+//   gather  C = R(:, I) (read as conj of rows I of the Hermitian R), core
+//   gram    partial sums of A^H B over 128-row chunks, FP64
+//   small   one workgroup per frame: chunk sums, Jacobi eigen-solves, small
+//           products, in FP64 (LDS-resident up to n = 64)
+//   apply   V = Y T (complex64) or U_s = C T_f (complex128 + FP32 copy)
+#include "fm_internal.h"
+
+namespace fm {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr double kRcondOrth = 64.0 * 2.220446049250313e-16;  // orth(): drop exact zeros
+constexpr int kMaxSweeps = 40;
+
+template <bool kBatched>
+__device__ __forceinline__ const FrameDev &frame_of(const FrameDev &single,
+                                                    const FrameDev *frames,
+                                                    const Item *items, int &a, int &b) {
+  if constexpr (kBatched) {
+    const Item &it = items[blockIdx.x];
+    a = it.a;
+    b = it.b;
+    return frames[it.frame];
+  } else {
+    a = blockIdx.x;
+    b = 0;
+    return single;
+  }
+}
+
+__device__ inline unsigned *wstat_of(const FrameDev &f) {
+  return reinterpret_cast<unsigned *>(f.small + (size_t)kSmallSlots * f.npad * f.npad);
+}
+__device__ inline double2 *slot(const FrameDev &f, int s) {
+  return f.small + (size_t)s * f.npad * f.npad;
+}
+enum Slot { kSlotT = 0, kSlotCore = 1, kSlotGc = 2, kSlotP = 3, kSlotZ = 4, kSlotA = 5, kSlotV = 6 };
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// ---------------------------------------------------------------------------
+// omega: real Gaussian test matrix -> complex operand
+// ---------------------------------------------------------------------------
+template <bool kBatched>
+__global__ __launch_bounds__(256) void omega_kernel(FrameDev single, const FrameDev *frames,
+                                                    const Item *items, int to_y) {
+  int chunk, unused;
+  const FrameDev &f = frame_of<kBatched>(single, frames, items, chunk, unused);
+  const int n = f.n;
+  const int m0 = chunk * kApplyRows;
+  const int mend = min(f.M, m0 + kApplyRows);
+  (void)to_y;
+  // q = 0: V = orth(Omega) comes first, so Omega goes to Y; else V = Omega
+  float2 *dst = f.q == 0 ? f.Y : f.V;
+  for (int e = threadIdx.x; e < (mend - m0) * n; e += blockDim.x) {
+    const int m = m0 + e / n, c = e % n;
+    dst[(size_t)m * n + c] = make_float2(f.Omega[(size_t)m * n + c], 0.f);
+  }
+  if (chunk == 0 && threadIdx.x == 0) *wstat_of(f) = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// sketch: Y = R V on FP32 MFMA.  One wave = 32 rows of R, all 2n real output
+// columns (n real parts, then n imaginary parts) in NB blocks of 32:
+//   Re Y = Rr Vr - Ri Vi,  Im Y = Rr Vi + Ri Vr
+// Each lane owns 4 consecutive elements of its row per step (the two
+// half-waves cover 8 consecutive columns of R), which is both the MFMA K
+// index and a contiguous 32-byte load.
+// ---------------------------------------------------------------------------
+template <int NB>
+__device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 31, h = lane >> 5;
+  const int M = f.M, n = f.n;
+  const int row = min(i0 + r, M - 1);
+  const float2 *pr = f.R + (size_t)row * f.ldr + 4 * h;
+  int col[NB], part[NB];
+  bool okc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int nn = 32 * b + r;
+    okc[b] = nn < 2 * n;
+    part[b] = nn < n ? 0 : 1;
+    col[b] = okc[b] ? (nn < n ? nn : nn - n) : 0;
+  }
+  floatx16 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
+
+  const float2 *V = f.V;
+  auto step = [&](const float2 (&a)[4], int mb, int mlim) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int m = mb + 4 * h + s;
+      const bool okm = m < mlim;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        float2 v = (okm && okc[b]) ? V[(size_t)m * n + col[b]] : make_float2(0.f, 0.f);
+        const float bre = part[b] == 0 ? v.x : v.y;
+        const float bim = part[b] == 0 ? -v.y : v.x;
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s].x, bre, acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s].y, bim, acc[b], 0, 0, 0);
+      }
+    }
+  };
+  const int Mfull = M & ~7;
+  for (int m0 = 0; m0 < Mfull; m0 += 8) {
+    float2 a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[s] = pr[m0 + s];
+    step(a, m0, M);
+  }
+  if (Mfull < M) {
+    float2 a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      a[s] = (Mfull + 4 * h + s < M) ? pr[Mfull + s] : make_float2(0.f, 0.f);
+    step(a, Mfull, M);
+  }
+  float *Yf = reinterpret_cast<float *>(f.Y);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if (!okc[b]) continue;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = i0 + (v >> 2) * 8 + h * 4 + (v & 3);
+      if (i < M) Yf[((size_t)i * n + col[b]) * 2 + part[b]] = acc[b][v];
+    }
+  }
+}
+
+template <bool kBatched>
+__global__ __launch_bounds__(256) void sketch_kernel(FrameDev single, const FrameDev *frames,
+                                                     const Item *items) {
+  int blk, unused;
+  const FrameDev &f = frame_of<kBatched>(single, frames, items, blk, unused);
+  const int i0 = blk * kSketchRows + (threadIdx.x >> 6) * 32;
+  if (i0 >= f.M) return;
+  const int nb = (2 * f.n + 31) / 32;
+  switch (nb) {
+    case 1: sketch_rows<1>(f, i0); break;
+    case 2: sketch_rows<2>(f, i0); break;
+    case 3: sketch_rows<3>(f, i0); break;
+    default: sketch_rows<4>(f, i0); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gather (Method 1): C[m][j] = R[m][idx_j] = conj(R[idx_j][m]); chunk 0 also
+// forms core = R(I, I) in FP64 and checks the index set.
+// ---------------------------------------------------------------------------
+template <bool kBatched>
+__global__ __launch_bounds__(256) void gather_kernel(FrameDev single, const FrameDev *frames,
+                                                     const Item *items) {
+  int chunk, unused;
+  const FrameDev &f = frame_of<kBatched>(single, frames, items, chunk, unused);
+  const int n = f.n, M = f.M;
+  const int m0 = chunk * kApplyRows;
+  const int rows = min(M, m0 + kApplyRows) - m0;
+  for (int e = threadIdx.x; e < rows * n; e += blockDim.x) {
+    const int j = e / rows, m = m0 + e % rows;  // consecutive threads read along a row of R
+    const int ij = min(max(f.idx[j], 0), M - 1);
+    const float2 v = f.R[(size_t)ij * f.ldr + m];
+    f.Y[(size_t)m * n + j] = make_float2(v.x, -v.y);
+  }
+  if (chunk == 0) {
+    __shared__ unsigned bad;
+    if (threadIdx.x == 0) bad = 0u;
+    __syncthreads();
+    double2 *core = slot(f, kSlotCore);
+    const int np = f.npad;
+    for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+      const int a = e / np, b = e % np;
+      double2 v = make_double2(0.0, 0.0);
+      if (a < n && b < n) {
+        const int ia = f.idx[a], ib = f.idx[b];
+        if (ia < 0 || ia >= M || (a != b && ia == ib)) atomicOr(&bad, (unsigned)FM_ST_BAD_INDEX);
+        const float2 r = f.R[(size_t)min(max(ia, 0), M - 1) * f.ldr + min(max(ib, 0), M - 1)];
+        v = make_double2(r.x, r.y);
+      }
+      core[e] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *wstat_of(f) = bad;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gram: partial sums over a 128-row chunk of A^H B, FP64 accumulation of the
+// FP32 inputs (their products are exact in FP64).  Each thread owns a TB x TB
+// block of entries.
+// ---------------------------------------------------------------------------
+template <int TB>
+__device__ __forceinline__ void gram_block(const float2 *A, const float2 *B, double2 *out,
+                                           int n, int m0, int m1) {
+  const int nbk = (n + TB - 1) / TB;
+  for (int blk = threadIdx.x; blk < nbk * nbk; blk += blockDim.x) {
+    const int a0 = (blk / nbk) * TB, b0 = (blk % nbk) * TB;
+    double2 acc[TB][TB];
+#pragma unroll
+    for (int x = 0; x < TB; ++x)
+#pragma unroll
+      for (int y = 0; y < TB; ++y) acc[x][y] = make_double2(0.0, 0.0);
+    for (int m = m0; m < m1; ++m) {
+      float2 av[TB], bv[TB];
+#pragma unroll
+      for (int x = 0; x < TB; ++x) {
+        av[x] = (a0 + x < n) ? A[(size_t)m * n + a0 + x] : make_float2(0.f, 0.f);
+        bv[x] = (b0 + x < n) ? B[(size_t)m * n + b0 + x] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int x = 0; x < TB; ++x)
+#pragma unroll
+        for (int y = 0; y < TB; ++y) {
+          const double ar = av[x].x, ai = av[x].y, br = bv[y].x, bi = bv[y].y;
+          acc[x][y].x = fma(ar, br, acc[x][y].x);
+          acc[x][y].x = fma(ai, bi, acc[x][y].x);
+          acc[x][y].y = fma(ar, bi, acc[x][y].y);
+          acc[x][y].y = fma(-ai, br, acc[x][y].y);
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < TB; ++x)
+#pragma unroll
+      for (int y = 0; y < TB; ++y)
+        if (a0 + x < n && b0 + y < n) out[(size_t)(a0 + x) * n + b0 + y] = acc[x][y];
+  }
+}
+
+template <bool kBatched>
+__global__ __launch_bounds__(256) void gram_kernel(FrameDev single, const FrameDev *frames,
+                                                   const Item *items, int mode) {
+  int chunk, unused;
+  const FrameDev &f = frame_of<kBatched>(single, frames, items, chunk, unused);
+  const int n = f.n;
+  const int m0 = chunk * kGramRows, m1 = min(f.M, m0 + kGramRows);
+  double2 *p0 = f.part + (size_t)(chunk * 2 + 0) * n * n;
+  double2 *p1 = f.part + (size_t)(chunk * 2 + 1) * n * n;
+  const int tb = (n <= 16) ? 1 : (n <= 32 ? 2 : 4);
+  auto run = [&](const float2 *A, const float2 *B, double2 *out) {
+    if (tb == 1) gram_block<1>(A, B, out, n, m0, m1);
+    else if (tb == 2) gram_block<2>(A, B, out, n, m0, m1);
+    else gram_block<4>(A, B, out, n, m0, m1);
+  };
+  if (mode == kGramSelf) {
+    run(f.Y, f.Y, p0);
+  } else if (f.method == FM_METHOD_PROJECT) {
+    run(f.V, f.Y, p0);   // core = V^H (R V)
+    run(f.Y, f.Y, p1);   // C^H C
+  } else {
+    run(f.Y, f.Y, p1);   // C^H C (core comes from the gather)
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small dense: Jacobi eigen-solver for a Hermitian matrix, one workgroup
+// ---------------------------------------------------------------------------
+struct Rot {
+  double2 jpp, jpq, jqp, jqq;
+  double ap, aq;
+  int p, q, mode;  // mode 0: identity, 1: rotate, 2: identity + zero A_pq
+};
+
+__device__ inline int rr_index(int pos, int round, int np) {
+  return pos == 0 ? 0 : 1 + (pos - 1 + round) % (np - 1);
+}
+
+// Block reduction of one double per thread in a fixed tree order.
+__device__ double block_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Cyclic Jacobi with round-robin (parallel) ordering on an np x np Hermitian
+// matrix A (np even; rows/columns >= n are zero padding).  V accumulates the
+// rotations (must start as the identity).  A becomes diagonal.  Returns the
+// number of sweeps or -1 at the sweep limit.
+__device__ int jacobi_eigh(double2 *A, double2 *V, int np, Rot *rot, double *red) {
+  const int nh = np / 2;
+  for (int sweep = 0;; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+      const double2 v = A[e];
+      const double a2 = v.x * v.x + v.y * v.y;
+      tot += a2;
+      if (e / np != e % np) off += a2;
+    }
+    off = block_sum(off, red);
+    tot = block_sum(tot, red);
+    if (off == 0.0 || off <= 1e-30 * tot) return sweep;
+    if (sweep == kMaxSweeps) return -1;
+    for (int round = 0; round < np - 1; ++round) {
+      for (int k = threadIdx.x; k < nh; k += blockDim.x) {
+        int p = rr_index(k, round, np), q = rr_index(np - 1 - k, round, np);
+        if (p > q) { const int t = p; p = q; q = t; }
+        Rot R;
+        R.p = p;
+        R.q = q;
+        R.jpp = make_double2(1.0, 0.0);
+        R.jpq = make_double2(0.0, 0.0);
+        R.jqp = make_double2(0.0, 0.0);
+        R.jqq = make_double2(1.0, 0.0);
+        R.ap = A[(size_t)p * np + p].x;
+        R.aq = A[(size_t)q * np + q].x;
+        R.mode = 0;
+        const double2 b = A[(size_t)p * np + q];
+        const double ab = sqrt(b.x * b.x + b.y * b.y);
+        if (ab > 0.0) {
+          if (ab <= 1e-18 * sqrt(fabs(R.ap) * fabs(R.aq))) {
+            R.mode = 2;
+          } else {
+            const double z = (R.aq - R.ap) / (2.0 * ab);
+            const double t = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+            const double c = 1.0 / sqrt(1.0 + t * t);
+            const double s = t * c;
+            const double2 e = make_double2(b.x / ab, -b.y / ab);  // e^{-i phi}
+            R.jpp = make_double2(c, 0.0);
+            R.jpq = make_double2(s, 0.0);
+            R.jqp = make_double2(-s * e.x, -s * e.y);
+            R.jqq = make_double2(c * e.x, c * e.y);
+            R.ap = R.ap - t * ab;
+            R.aq = R.aq + t * ab;
+            R.mode = 1;
+          }
+        }
+        rot[k] = R;
+      }
+      __syncthreads();
+      // A <- J^H A J on 2x2 blocks (rows of pair ki, columns of pair kj)
+      for (int e = threadIdx.x; e < nh * nh; e += blockDim.x) {
+        const int ki = e / nh, kj = e % nh;
+        const Rot &Ri = rot[ki];
+        const Rot &Rj = rot[kj];
+        const size_t pp = (size_t)Ri.p * np + Rj.p, pq = (size_t)Ri.p * np + Rj.q;
+        const size_t qp = (size_t)Ri.q * np + Rj.p, qq = (size_t)Ri.q * np + Rj.q;
+        if (ki == kj) {
+          if (Ri.mode == 1) {
+            A[pp] = make_double2(Ri.ap, 0.0);
+            A[qq] = make_double2(Ri.aq, 0.0);
+            A[pq] = make_double2(0.0, 0.0);
+            A[qp] = make_double2(0.0, 0.0);
+          } else if (Ri.mode == 2) {
+            A[pq] = make_double2(0.0, 0.0);
+            A[qp] = make_double2(0.0, 0.0);
+          }
+          continue;
+        }
+        if (Ri.mode != 1 && Rj.mode != 1) continue;
+        const double2 b00 = A[pp], b01 = A[pq], b10 = A[qp], b11 = A[qq];
+        // C = B J_j
+        const double2 c00 = cadd(cmul(b00, Rj.jpp), cmul(b01, Rj.jqp));
+        const double2 c01 = cadd(cmul(b00, Rj.jpq), cmul(b01, Rj.jqq));
+        const double2 c10 = cadd(cmul(b10, Rj.jpp), cmul(b11, Rj.jqp));
+        const double2 c11 = cadd(cmul(b10, Rj.jpq), cmul(b11, Rj.jqq));
+        // D = J_i^H C
+        A[pp] = cadd(cmulc(Ri.jpp, c00), cmulc(Ri.jqp, c10));
+        A[pq] = cadd(cmulc(Ri.jpp, c01), cmulc(Ri.jqp, c11));
+        A[qp] = cadd(cmulc(Ri.jpq, c00), cmulc(Ri.jqq, c10));
+        A[qq] = cadd(cmulc(Ri.jpq, c01), cmulc(Ri.jqq, c11));
+      }
+      // V <- V J
+      for (int e = threadIdx.x; e < nh * np; e += blockDim.x) {
+        const int kj = e / np, row = e % np;
+        const Rot &Rj = rot[kj];
+        if (Rj.mode != 1) continue;
+        const size_t ip = (size_t)row * np + Rj.p, iq = (size_t)row * np + Rj.q;
+        const double2 vp = V[ip], vq = V[iq];
+        V[ip] = cadd(cmul(vp, Rj.jpp), cmul(vq, Rj.jqp));
+        V[iq] = cadd(cmul(vp, Rj.jpq), cmul(vq, Rj.jqq));
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Descending order of the diagonal of A (first n entries); ties keep index
+// order.  perm[k] = index of the k-th largest.  w[k] = its value.
+__device__ void sort_desc(const double2 *A, int np, int n, int *perm, double *w) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double wi = A[(size_t)i * np + i].x;
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double wj = A[(size_t)j * np + j].x;
+      rank += (wj > wi) || (wj == wi && j < i);
+    }
+    perm[rank] = i;
+    w[rank] = wi;
+  }
+  __syncthreads();
+}
+
+// LDS footprint of the small kernel for matrices up to NMAX (0: global).
+template <int NMAX>
+struct SmallLds {
+  static constexpr int kMat = NMAX > 0 ? NMAX * NMAX : 1;
+  double2 A[kMat];
+  double2 V[kMat];
+  Rot rot[NMAX > 0 ? NMAX / 2 : kMaxN / 2];
+  double red[256];
+  double w[kMaxN];
+  int perm[kMaxN];
+  int rank;
+  unsigned st;
+};
+
+// Load a Hermitian matrix: sum of Gram partials (fixed chunk order) or a slot,
+// symmetrised, zero padded to np x np; V = I.
+__device__ void load_herm(double2 *A, double2 *V, int np, int n, const double2 *part,
+                          int nchunk, int which, const double2 *src) {
+  for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+    const int i = e / np, j = e % np;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < n && j < n) {
+      double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+      if (part) {
+        for (int c = 0; c < nchunk; ++c) {
+          const double2 *pc = part + (size_t)(c * 2 + which) * n * n;
+          a = cadd(a, pc[(size_t)i * n + j]);
+          b = cadd(b, pc[(size_t)j * n + i]);
+        }
+      } else {
+        a = src[(size_t)i * np + j];
+        b = src[(size_t)j * np + i];
+      }
+      // (A + A^H) / 2
+      v = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
+    }
+    A[e] = v;
+    V[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+}
+
+template <int NMAX, bool kBatched>
+__global__ __launch_bounds__(256) void small_kernel(FrameDev single, const FrameDev *frames,
+                                                    const Item *items, int mode) {
+  int unused_a, unused_b;
+  const FrameDev &f = frame_of<kBatched>(single, frames, items, unused_a, unused_b);
+  __shared__ SmallLds<NMAX> S;
+  const int n = f.n, np = f.npad;
+  double2 *A = NMAX > 0 ? S.A : slot(f, kSlotA);
+  double2 *V = NMAX > 0 ? S.V : slot(f, kSlotV);
+  if (threadIdx.x == 0) S.st = 0u;
+
+  if (mode == kOrth) {
+    // V_new = Y E diag(lambda^-1/2): orthonormal basis of the sketch
+    load_herm(A, V, np, n, f.part, f.nchunk, 0, nullptr);
+    const int sw = jacobi_eigh(A, V, np, S.rot, S.red);
+    sort_desc(A, np, n, S.perm, S.w);
+    double2 *T = slot(f, kSlotT);
+    const double thr = kRcondOrth * S.w[0];
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int i = e / n, k = e % n;
+      const double lam = S.w[k];
+      double2 v = make_double2(0.0, 0.0);
+      if (lam > 0.0 && lam > thr) {
+        const double sc = 1.0 / sqrt(lam);
+        const double2 x = V[(size_t)i * np + S.perm[k]];
+        v = make_double2(x.x * sc, x.y * sc);
+      }
+      T[e] = v;
+    }
+    if (threadIdx.x == 0 && sw < 0) *wstat_of(f) |= FM_ST_EIG_MAXIT;
+    return;
+  }
+
+  // ---- final: core -> P, H = P^H Gc P -> W, sigma; T_f = P W_K sigma^-1/2 ----
+  const bool sample = f.method == FM_METHOD_SAMPLE;
+  // Gc (sum of partials, symmetrised) parked in its slot
+  double2 *Gc = slot(f, kSlotGc);
+  for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+    const int i = e / np, j = e % np;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < n && j < n) {
+      double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+      for (int c = 0; c < f.nchunk; ++c) {
+        const double2 *pc = f.part + (size_t)(c * 2 + 1) * n * n;
+        a = cadd(a, pc[(size_t)i * n + j]);
+        b = cadd(b, pc[(size_t)j * n + i]);
+      }
+      v = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
+    }
+    Gc[e] = v;
+  }
+  if (sample) load_herm(A, V, np, n, nullptr, 0, 0, slot(f, kSlotCore));
+  else load_herm(A, V, np, n, f.part, f.nchunk, 0, nullptr);
+  int sw = jacobi_eigh(A, V, np, S.rot, S.red);
+  if (threadIdx.x == 0 && sw < 0) S.st |= FM_ST_EIG_MAXIT;
+  sort_desc(A, np, n, S.perm, S.w);
+  if (threadIdx.x == 0) {
+    const double thr = f.rcond * S.w[0];
+    int r = 0;
+    for (int k = 0; k < n; ++k)
+      if (S.w[k] > thr && S.w[k] > 0.0) ++r;
+    S.rank = r;
+  }
+  __syncthreads();
+  const int r1 = S.rank;
+  const int rp = (r1 + 1) & ~1;
+  // P = E_r diag(lambda^-1/2)   (n x r1, ld np)
+  double2 *P = slot(f, kSlotP);
+  for (int e = threadIdx.x; e < n * np; e += blockDim.x) {
+    const int i = e / np, k = e % np;
+    double2 v = make_double2(0.0, 0.0);
+    if (k < r1) {
+      const double sc = 1.0 / sqrt(S.w[k]);
+      const double2 x = V[(size_t)i * np + S.perm[k]];
+      v = make_double2(x.x * sc, x.y * sc);
+    }
+    P[e] = v;
+  }
+  __syncthreads();
+  // Z = Gc P  (n x r1)
+  double2 *Z = slot(f, kSlotZ);
+  for (int e = threadIdx.x; e < n * r1; e += blockDim.x) {
+    const int i = e / r1, k = e % r1;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < n; ++j) acc = cadd(acc, cmul(Gc[(size_t)i * np + j], P[(size_t)j * np + k]));
+    Z[(size_t)i * np + k] = acc;
+  }
+  __syncthreads();
+  // H = P^H Z  (r1 x r1, padded to rp), into A; V = I
+  for (int e = threadIdx.x; e < rp * rp; e += blockDim.x) {
+    const int a = e / rp, b = e % rp;
+    double2 acc = make_double2(0.0, 0.0);
+    if (a < r1 && b < r1)
+      for (int j = 0; j < n; ++j)
+        acc = cadd(acc, cmulc(P[(size_t)j * np + a], Z[(size_t)j * np + b]));
+    A[e] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < rp * rp; e += blockDim.x) {
+    const int a = e / rp, b = e % rp;
+    if (a < r1 && b < r1 && a <= b) {
+      const double2 x = A[(size_t)a * rp + b], y = A[(size_t)b * rp + a];
+      const double2 h = make_double2(0.5 * (x.x + y.x), a == b ? 0.0 : 0.5 * (x.y - y.y));
+      A[(size_t)a * rp + b] = h;
+      A[(size_t)b * rp + a] = make_double2(h.x, -h.y);
+    }
+    V[e] = make_double2(a == b ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  if (rp > 0) {
+    sw = jacobi_eigh(A, V, rp, S.rot, S.red);
+    if (threadIdx.x == 0 && sw < 0) S.st |= FM_ST_EIG_MAXIT;
+    sort_desc(A, rp, r1, S.perm, S.w);
+  }
+  // T_f = P W_K diag(sigma^-1/2)  (n x K, ld K)
+  const int K = f.K;
+  double2 *Tf = slot(f, kSlotT);
+  for (int e = threadIdx.x; e < n * K; e += blockDim.x) {
+    const int i = e / K, k = e % K;
+    double2 acc = make_double2(0.0, 0.0);
+    if (k < r1 && S.w[k] > 0.0) {
+      const int col = S.perm[k];
+      for (int j = 0; j < r1; ++j) acc = cadd(acc, cmul(P[(size_t)i * np + j], V[(size_t)j * rp + col]));
+      const double sc = 1.0 / sqrt(S.w[k]);
+      acc = make_double2(acc.x * sc, acc.y * sc);
+    }
+    Tf[e] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned st = S.st | *wstat_of(f);
+    for (int k = 0; k < K; ++k) {
+      const bool ok = k < r1 && S.w[k] > 0.0;
+      f.sigma[k] = ok ? S.w[k] : 0.0;
+      if (!ok) st |= FM_ST_RANK_DEFICIENT;
+    }
+    *f.status = st;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// apply: V = Y T (ORTH, complex64 [M][n]) or U_s = C T_f (FINAL, complex128
+// [K][M] plus the FP32 copy Uf [M][K] used by the spectrum pass)
+// ---------------------------------------------------------------------------
+template <bool kBatched>
+__global__ __launch_bounds__(256) void apply_kernel(FrameDev single, const FrameDev *frames,
+                                                    const Item *items, int mode) {
+  int chunk, unused;
+  const FrameDev &f = frame_of<kBatched>(single, frames, items, chunk, unused);
+  const int n = f.n, M = f.M;
+  const int m0 = chunk * kApplyRows;
+  const int rows = min(M, m0 + kApplyRows) - m0;
+  const double2 *Tm = slot(f, kSlotT);
+  const int ncol = mode == kApplyV ? n : f.K;
+  for (int e = threadIdx.x; e < rows * ncol; e += blockDim.x) {
+    const int c = e / rows, m = m0 + e % rows;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < n; ++j) {
+      const float2 y = f.Y[(size_t)m * n + j];
+      const double2 t = Tm[(size_t)j * ncol + c];
+      acc.x = fma((double)y.x, t.x, acc.x);
+      acc.x = fma(-(double)y.y, t.y, acc.x);
+      acc.y = fma((double)y.x, t.y, acc.y);
+      acc.y = fma((double)y.y, t.x, acc.y);
+    }
+    if (mode == kApplyV) {
+      f.V[(size_t)m * n + c] = make_float2((float)acc.x, (float)acc.y);
+    } else {
+      f.Us[(size_t)c * M + m] = acc;
+      f.Uf[(size_t)m * ncol + c] = make_float2((float)acc.x, (float)acc.y);
+    }
+  }
+}
+
+inline dim3 grid1(const FrameDev &single, const Item *items, int n_items, int per_frame) {
+  return dim3(items ? n_items : per_frame);
+}
+
+}  // namespace
+
+hipError_t launch_omega(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, int to_y, hipStream_t s) {
+  const int per = (single.M + kApplyRows - 1) / kApplyRows;
+  if (items) hipLaunchKernelGGL(omega_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames, items, to_y);
+  else hipLaunchKernelGGL(omega_kernel<false>, dim3(per), dim3(256), 0, s, single, frames, items, to_y);
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch(const FrameDev &single, const FrameDev *frames, const Item *items,
+                         int n_items, fm_prec prec, hipStream_t s) {
+  (void)prec;
+  const int per = (single.M + kSketchRows - 1) / kSketchRows;
+  if (items) hipLaunchKernelGGL(sketch_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames, items);
+  else hipLaunchKernelGGL(sketch_kernel<false>, dim3(per), dim3(256), 0, s, single, frames, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const FrameDev &single, const FrameDev *frames, const Item *items,
+                         int n_items, hipStream_t s) {
+  const int per = (single.M + kApplyRows - 1) / kApplyRows;
+  if (items) hipLaunchKernelGGL(gather_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames, items);
+  else hipLaunchKernelGGL(gather_kernel<false>, dim3(per), dim3(256), 0, s, single, frames, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const FrameDev &single, const FrameDev *frames, const Item *items,
+                       int n_items, int mode, hipStream_t s) {
+  const int per = (single.M + kGramRows - 1) / kGramRows;
+  if (items) hipLaunchKernelGGL(gram_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames, items, mode);
+  else hipLaunchKernelGGL(gram_kernel<false>, dim3(per), dim3(256), 0, s, single, frames, items, mode);
+  return hipGetLastError();
+}
+
+// The plan sorts frames by n; each launch covers frames of one LDS class.
+hipError_t launch_small(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, int mode, hipStream_t s) {
+  // class of the launch = the largest n among its frames, passed in single.n
+  const int n = single.n;
+  const dim3 g(items ? n_items : 1), b(256);
+  if (n <= 16) {
+    if (items) hipLaunchKernelGGL((small_kernel<16, true>), g, b, 0, s, single, frames, items, mode);
+    else hipLaunchKernelGGL((small_kernel<16, false>), g, b, 0, s, single, frames, items, mode);
+  } else if (n <= 32) {
+    if (items) hipLaunchKernelGGL((small_kernel<32, true>), g, b, 0, s, single, frames, items, mode);
+    else hipLaunchKernelGGL((small_kernel<32, false>), g, b, 0, s, single, frames, items, mode);
+  } else if (n <= kSmallLdsN) {
+    if (items) hipLaunchKernelGGL((small_kernel<kSmallLdsN, true>), g, b, 0, s, single, frames, items, mode);
+    else hipLaunchKernelGGL((small_kernel<kSmallLdsN, false>), g, b, 0, s, single, frames, items, mode);
+  } else {
+    if (items) hipLaunchKernelGGL((small_kernel<0, true>), g, b, 0, s, single, frames, items, mode);
+    else hipLaunchKernelGGL((small_kernel<0, false>), g, b, 0, s, single, frames, items, mode);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, int mode, hipStream_t s) {
+  const int per = (single.M + kApplyRows - 1) / kApplyRows;
+  if (items) hipLaunchKernelGGL(apply_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames, items, mode);
+  else hipLaunchKernelGGL(apply_kernel<false>, dim3(per), dim3(256), 0, s, single, frames, items, mode);
+  return hipGetLastError();
+}
+
+}  // namespace fm

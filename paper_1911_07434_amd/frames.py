@@ -1,0 +1,97 @@
+"""Device buffers of one frame and its fm_frame descriptor.
+
+A DeviceFrame owns (as torch tensors on the GPU) the inputs, outputs and
+randomness of one frame and builds the fm_frame record a Plan consumes.  It
+does no arithmetic of its own.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import FM_METHOD_PROJECT, FM_METHOD_SAMPLE, FM_RCOND_DEFAULT, fm_frame
+
+
+@dataclass
+class FrameSpec:
+    M: int
+    T: int
+    K: int
+    method: int = FM_METHOD_PROJECT
+    n: int = 16            # l (Method 2) or p (Method 1)
+    q: int = 2
+    L: int = 18001
+    theta0_deg: float = -90.0
+    dtheta_deg: float = 0.01
+    rcond: float = FM_RCOND_DEFAULT
+
+
+class DeviceFrame:
+    def __init__(self, spec: FrameSpec, X=None, rnd=None, device="cuda"):
+        import torch
+        s = spec
+        self.spec = s
+        dev = torch.device(device)
+        self.X = (torch.as_tensor(X).to(dev) if X is not None
+                  else torch.empty((s.M, s.T), dtype=torch.complex64, device=dev))
+        self.R = torch.empty((s.M, s.M), dtype=torch.complex64, device=dev)
+        if s.method == FM_METHOD_PROJECT:
+            self.Omega = (torch.as_tensor(rnd).to(dev) if rnd is not None
+                          else torch.empty((s.M, s.n), dtype=torch.float32, device=dev))
+            self.idx = None
+        else:
+            self.idx = (torch.as_tensor(np.asarray(rnd, np.int32)).to(dev) if rnd is not None
+                        else torch.empty((s.n,), dtype=torch.int32, device=dev))
+            self.Omega = None
+        self.Us = torch.zeros((s.K, s.M), dtype=torch.complex128, device=dev)
+        self.sigma = torch.zeros((s.K,), dtype=torch.float64, device=dev)
+        self.status = torch.zeros((1,), dtype=torch.int32, device=dev)
+        self.P = torch.zeros((s.L,), dtype=torch.float32, device=dev)
+        self.peak_idx = torch.zeros((s.K,), dtype=torch.int32, device=dev)
+        self.peak_val = torch.zeros((s.K,), dtype=torch.float32, device=dev)
+        self.n_found = torch.zeros((1,), dtype=torch.int32, device=dev)
+
+    def descriptor(self) -> fm_frame:
+        s = self.spec
+        f = fm_frame()
+        f.X = self.X.data_ptr()
+        f.ldx = self.X.stride(0)
+        f.M, f.T = s.M, s.T
+        f.R = self.R.data_ptr()
+        f.ldr = self.R.stride(0)
+        f.K, f.method, f.n, f.q = s.K, s.method, s.n, s.q
+        f.rcond = s.rcond
+        f.Omega = self.Omega.data_ptr() if self.Omega is not None else None
+        f.idx = self.idx.data_ptr() if self.idx is not None else None
+        f.Us = self.Us.data_ptr()
+        f.sigma = self.sigma.data_ptr()
+        f.status = self.status.data_ptr()
+        f.L = s.L
+        f.theta0_deg, f.dtheta_deg = s.theta0_deg, s.dtheta_deg
+        f.P = self.P.data_ptr()
+        f.peak_idx = self.peak_idx.data_ptr()
+        f.peak_val = self.peak_val.data_ptr()
+        f.n_found = self.n_found.data_ptr()
+        return f
+
+    def results(self) -> dict:
+        """Copy the outputs back to host numpy arrays."""
+        nf = int(self.n_found.cpu()[0])
+        return dict(R=self.R.cpu().numpy(), Us=self.Us.cpu().numpy(),
+                    sigma=self.sigma.cpu().numpy(), status=int(self.status.cpu()[0]),
+                    P=self.P.cpu().numpy(), peak_idx=self.peak_idx.cpu().numpy()[:nf],
+                    peak_val=self.peak_val.cpu().numpy()[:nf], n_found=nf)
+
+
+def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
+    """All four stages of one frame through the single-frame entry points."""
+    s = fr.spec
+    ctx.fm_covariance(fr.X, fr.R, prec, stream)
+    if s.method == FM_METHOD_PROJECT:
+        ctx.fm_subspace_project(fr.R, fr.Omega, s.q, s.K, fr.Us, fr.sigma, fr.status, s.rcond,
+                                prec, stream)
+    else:
+        ctx.fm_subspace_sample(fr.R, fr.idx, s.K, fr.Us, fr.sigma, fr.status, s.rcond, stream)
+    ctx.fm_pseudospectrum(fr.Us, s.theta0_deg, s.dtheta_deg, s.L, fr.P, prec, stream)
+    ctx.fm_peaks(fr.P, s.K, fr.peak_idx, fr.peak_val, fr.n_found, stream)

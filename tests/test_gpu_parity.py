@@ -1,0 +1,400 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (written in each test):
+  * covariance: bit-exact on small-integer frames with power-of-two T;
+    relative Frobenius error <= 1e-6 otherwise (FP32 accumulation);
+  * pseudo-spectrum: max |10 log10(P_gpu / P_oracle)| <= 1e-3 dB on the FP32
+    path, both for the spectrum stage alone (same U_s bits) and end to end;
+  * peaks: bit-exact on identical float32 spectra; end to end, every oracle
+    peak within one grid step of a GPU peak and the same count;
+  * subspace: projector distance small and the spectra of both subspaces
+    within 1e-3 dB;
+  * a frame gives bit-identical results alone and inside an uneven batch.
+"""
+import numpy as np
+import pytest
+
+import fmsynth
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1911_07434_amd as fm  # noqa: E402
+from paper_1911_07434_amd.frames import DeviceFrame, FrameSpec, run_single  # noqa: E402
+
+DB_FP32 = 1e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = fm.Context(0, 256 << 20)
+    yield c
+    c.close()
+
+
+def db_err(Pg, Po):
+    return float(np.max(np.abs(10.0 * np.log10(np.asarray(Pg, np.float64) / Po))))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def proj(Us):
+    return Us.T @ Us.conj()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ----------------------------------------------------------------------------
+# stage 1: covariance
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M,T", [(8, 64), (200, 512), (129, 1024), (256, 2048)])
+def test_covariance_integer_bitwise(ctx, M, T):
+    say(f"cov int M={M} T={T}")
+    X = fmsynth.make_integer_frame(M, T, seed=M + T)
+    R = torch.empty((M, M), dtype=torch.complex64, device="cuda")
+    ctx.fm_covariance(dev(X), R)
+    torch.cuda.synchronize()
+    Rg = R.cpu().numpy()
+    Ro = oracle.covariance(X)
+    assert np.array_equal(Rg.astype(np.complex128), Ro)
+
+
+@pytest.mark.parametrize("M,T", [(64, 128), (300, 777), (1, 5), (130, 3), (1024, 2048)])
+def test_covariance_gaussian(ctx, M, T):
+    say(f"cov gauss M={M} T={T}")
+    fr = fmsynth.make_frame(M, T, min(3, M), 0.0, seed=M * 7 + T)
+    R = torch.empty((M, M), dtype=torch.complex64, device="cuda")
+    ctx.fm_covariance(dev(fr.X), R)
+    torch.cuda.synchronize()
+    Rg = R.cpu().numpy()
+    Ro = oracle.covariance(fr.X, threads=oracle.default_threads())
+    err = np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)
+    assert err <= 1e-6
+    assert np.array_equal(Rg, Rg.conj().T)
+    assert np.all(np.diag(Rg).imag == 0)
+
+
+def test_covariance_leading_dimensions(ctx):
+    M, T = 70, 90
+    fr = fmsynth.make_frame(M, T, 2, 5.0, seed=3)
+    Xbig = np.zeros((M, T + 13), np.complex64)
+    Xbig[:, :T] = fr.X
+    Xd = dev(Xbig)
+    Rbig = torch.zeros((M, M + 5), dtype=torch.complex64, device="cuda")
+    lib = ctx.lib
+    st = lib.fm_covariance(ctx.h, fm._stream(), Xd.data_ptr(), M, T, T + 13, Rbig.data_ptr(),
+                           M + 5, fm.FM_FP32)
+    assert st == fm.FM_OK
+    torch.cuda.synchronize()
+    Rg = Rbig.cpu().numpy()
+    Ro = oracle.covariance(fr.X)
+    assert np.linalg.norm(Rg[:, :M] - Ro) / np.linalg.norm(Ro) <= 1e-6
+    assert np.all(Rg[:, M:] == 0)
+
+
+# ----------------------------------------------------------------------------
+# stage 3: pseudo-spectrum on the same U_s bits
+# ----------------------------------------------------------------------------
+
+def _spectrum_case(ctx, Us, th0, dth, L):
+    K, M = Us.shape
+    P = torch.empty(L, dtype=torch.float32, device="cuda")
+    ctx.fm_pseudospectrum(dev(Us), th0, dth, L, P)
+    torch.cuda.synchronize()
+    Po, deno = oracle.pseudospectrum(Us, th0, dth, L, threads=oracle.default_threads())
+    return P.cpu().numpy(), Po, deno
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_spectrum_on_oracle_subspace(ctx, name):
+    cfg = fmsynth.CONFIGS[name]
+    say(f"spectrum {name}")
+    fr, _ = fmsynth.config_frame(name, seed=11)
+    R = oracle.covariance(fr.X, threads=oracle.default_threads())
+    Us, _, _ = oracle.subspace_project(R, fmsynth.make_omega(fr.M, cfg["l"], 11), cfg["q"], fr.K)
+    th0, dth, L = fmsynth.grid(cfg["L"])
+    Pg, Po, _ = _spectrum_case(ctx, Us, th0, dth, L)
+    assert db_err(Pg, Po) <= DB_FP32
+
+
+@pytest.mark.parametrize("M,K,L", [(2, 1, 7), (17, 5, 333), (100, 33, 1000), (256, 64, 4097)])
+def test_spectrum_random_orthonormal(ctx, M, K, L):
+    rng = np.random.default_rng(M + K)
+    Q, _ = np.linalg.qr(rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K)))
+    th0, dth = -80.0, 160.0 / max(L - 1, 1)
+    Pg, Po, _ = _spectrum_case(ctx, np.ascontiguousarray(Q.T), th0, dth, L)
+    assert db_err(Pg, Po) <= DB_FP32
+
+
+def test_spectrum_single_source_pole_and_dirichlet(ctx):
+    M, L = 512, 18001
+    th0, dth, _ = fmsynth.grid(L)
+    l0 = 12345
+    a0 = fmsynth.steering_matrix(M, [th0 + l0 * dth])[:, 0]
+    Pg, Po, _ = _spectrum_case(ctx, (a0 / np.sqrt(M))[None, :], th0, dth, L)
+    assert int(np.argmax(Pg)) == l0
+    ok = np.abs(np.arange(L) - l0) > 0
+    assert db_err(Pg[ok], Po[ok]) <= DB_FP32
+    # the pole is clamped to a finite value
+    assert np.isfinite(Pg[l0]) and Pg[l0] > 1e6
+
+
+# ----------------------------------------------------------------------------
+# stage 4: peaks on identical float32 spectra (bit-exact)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", range(6))
+def test_peaks_bitexact(ctx, case):
+    rng = np.random.default_rng(case)
+    L = [1, 2, 5, 1000, 18001, 40000][case]
+    K = [1, 2, 3, 8, 40, 64][case]
+    P = rng.integers(0, 6, size=L).astype(np.float32)      # many ties and plateaus
+    if case >= 3:
+        P = np.round(rng.random(L) * 50).astype(np.float32)
+    Pd = dev(P)
+    idx = torch.zeros(K, dtype=torch.int32, device="cuda")
+    val = torch.zeros(K, dtype=torch.float32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.fm_peaks(Pd, K, idx, val, nf)
+    torch.cuda.synchronize()
+    n = int(nf.cpu()[0])
+    oi, ov = oracle.peaks(P.astype(np.float64), K)
+    assert n == len(oi)
+    assert np.array_equal(idx.cpu().numpy()[:n], oi)
+    assert np.array_equal(val.cpu().numpy()[:n].astype(np.float64), ov)
+
+
+def test_peaks_many_local_maxima_fallback(ctx):
+    # alternating spectrum: L/2 local maxima, more than the LDS candidate list
+    L, K = 40001, 10
+    P = np.where(np.arange(L) % 2 == 0, 1.0, 0.0).astype(np.float32)
+    P += (np.arange(L) % 997).astype(np.float32) * 1e-3
+    Pd = dev(P)
+    idx = torch.zeros(K, dtype=torch.int32, device="cuda")
+    val = torch.zeros(K, dtype=torch.float32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.fm_peaks(Pd, K, idx, val, nf)
+    torch.cuda.synchronize()
+    oi, _ = oracle.peaks(P.astype(np.float64), K)
+    assert np.array_equal(idx.cpu().numpy()[: int(nf.cpu()[0])], oi)
+
+
+# ----------------------------------------------------------------------------
+# stage 2: subspace on the same covariance bits
+# ----------------------------------------------------------------------------
+
+def _subspace_case(ctx, R64, method, rnd, n, q, K):
+    M = R64.shape[0]
+    Rd = dev(R64.astype(np.complex64))
+    Us = torch.zeros((K, M), dtype=torch.complex128, device="cuda")
+    sig = torch.zeros(K, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    if method == "project":
+        ctx.fm_subspace_project(Rd, dev(rnd), q, K, Us, sig, st)
+    else:
+        ctx.fm_subspace_sample(Rd, dev(rnd), K, Us, sig, st)
+    torch.cuda.synchronize()
+    # the oracle consumes the same complex64 covariance bits
+    Rq = Rd.cpu().numpy().astype(np.complex128)
+    if method == "project":
+        Uo, so, _ = oracle.subspace_project(Rq, rnd, q, K)
+    else:
+        Uo, so, _ = oracle.subspace_sample(Rq, rnd, K)
+    return Us.cpu().numpy(), sig.cpu().numpy(), int(st.cpu()[0]), Uo, so
+
+
+@pytest.mark.parametrize("name,method", [("c1", "project"), ("c1", "sample"),
+                                         ("c2", "project"), ("c2", "sample")])
+def test_subspace_matches_oracle(ctx, name, method):
+    cfg = fmsynth.CONFIGS[name]
+    say(f"subspace {name} {method}")
+    fr, _ = fmsynth.config_frame(name, seed=23)
+    R = oracle.covariance(fr.X, threads=oracle.default_threads())
+    if method == "project":
+        rnd, n = fmsynth.make_omega(fr.M, cfg["l"], 23), cfg["l"]
+    else:
+        rnd, n = fmsynth.make_idx(fr.M, cfg["p"], 23), cfg["p"]
+    Ug, sg, st, Uo, so = _subspace_case(ctx, R, method, rnd, n, cfg["q"], fr.K)
+    assert st == 0
+    assert np.max(np.abs(Ug.conj() @ Ug.T - np.eye(fr.K))) <= 1e-9
+    assert np.linalg.norm(proj(Ug) - proj(Uo), 2) <= 1e-6
+    assert np.max(np.abs(sg - so) / so) <= 1e-6
+    th0, dth, L = fmsynth.grid(cfg["L"])
+    Pg, _ = oracle.pseudospectrum(Ug, th0, dth, L, threads=oracle.default_threads())
+    Po, _ = oracle.pseudospectrum(Uo, th0, dth, L, threads=oracle.default_threads())
+    assert db_err(Pg, Po) <= DB_FP32
+
+
+@pytest.mark.parametrize("M,K,n,q,method", [
+    (40, 3, 3, 0, "project"), (40, 3, 40, 1, "project"), (97, 1, 9, 3, "project"),
+    (65, 6, 64, 2, "project"), (40, 4, 40, 0, "sample"), (150, 5, 96, 0, "sample"),
+    (300, 7, 160, 0, "sample"), (33, 2, 2, 0, "sample")])
+def test_subspace_edge_shapes(ctx, M, K, n, q, method):
+    say(f"subspace edge M={M} K={K} n={n} q={q} {method}")
+    fr = fmsynth.make_frame(M, 2 * M, K, 10.0, seed=M + n, angle_range=(-60, 60), min_sep=3)
+    R = oracle.covariance(fr.X)
+    rnd = fmsynth.make_omega(M, n, M) if method == "project" else fmsynth.make_idx(M, n, M)
+    Ug, sg, st, Uo, so = _subspace_case(ctx, R, method, rnd, n, q, K)
+    assert st == 0
+    assert np.linalg.norm(proj(Ug) - proj(Uo), 2) <= 1e-5
+    assert np.max(np.abs(sg - so) / so) <= 1e-5
+
+
+def test_subspace_noiseless_rank_k(ctx):
+    # exactly rank-K covariance: both methods recover span(A) (Lemmas 5, 6)
+    M, K = 128, 4
+    th = np.array([-40.0, -12.5, 20.0, 55.0])
+    A = fmsynth.steering_matrix(M, th)
+    R = A @ A.conj().T
+    for method, rnd, n in (("project", fmsynth.make_omega(M, 12, 1), 12),
+                           ("sample", fmsynth.make_idx(M, 16, 1), 16)):
+        Ug, sg, st, Uo, so = _subspace_case(ctx, R, method, rnd, n, 2, K)
+        Qa, _ = np.linalg.qr(A)
+        assert st == 0
+        assert np.linalg.norm(proj(Ug) - Qa @ Qa.conj().T, 2) <= 1e-5
+
+
+def test_subspace_reports_bad_index_and_rank_deficiency(ctx):
+    M, K = 32, 3
+    fr = fmsynth.make_frame(M, 64, K, 10.0, seed=4)
+    R = oracle.covariance(fr.X)
+    idx = np.array([1, 5, 5, 9, 30], np.int32)
+    Ug, sg, st, _, _ = _subspace_case(ctx, R, "sample", idx, 5, 0, K)
+    assert st & fm.FM_ST_BAD_INDEX
+    # rank-1 covariance, K = 3: only one direction survives
+    a = fmsynth.steering_matrix(M, [10.0])
+    R1 = a @ a.conj().T
+    Ug, sg, st, _, _ = _subspace_case(ctx, R1, "project", fmsynth.make_omega(M, 6, 2), 6, 1, K)
+    assert st & fm.FM_ST_RANK_DEFICIENT
+    assert sg[1] == 0 and sg[2] == 0
+
+
+# ----------------------------------------------------------------------------
+# end to end: X -> peaks, single frame, against the oracle pipeline
+# ----------------------------------------------------------------------------
+
+def _end_to_end(ctx, name, method, seed):
+    cfg = fmsynth.CONFIGS[name]
+    fr, _ = fmsynth.config_frame(name, seed=seed)
+    th0, dth, L = fmsynth.grid(cfg["L"])
+    if method == "project":
+        rnd, n, m = fmsynth.make_omega(fr.M, cfg["l"], seed), cfg["l"], fm.FM_METHOD_PROJECT
+    else:
+        rnd, n, m = fmsynth.make_idx(fr.M, cfg["p"], seed), cfg["p"], fm.FM_METHOD_SAMPLE
+    spec = FrameSpec(M=fr.M, T=fr.T, K=fr.K, method=m, n=n, q=cfg["q"], L=L, theta0_deg=th0,
+                     dtheta_deg=dth)
+    d = DeviceFrame(spec, X=torch.from_numpy(fr.X), rnd=torch.from_numpy(rnd))
+    run_single(ctx, d)
+    torch.cuda.synchronize()
+    got = d.results()
+    kw = dict(Omega=rnd, q=cfg["q"]) if method == "project" else dict(idx=rnd)
+    ref = oracle.run_frame(fr.X, fr.K, method, th0, dth, L, threads=oracle.default_threads(), **kw)
+    return got, ref
+
+
+@pytest.mark.parametrize("name,method,seed", [("c1", "project", 1), ("c1", "sample", 2),
+                                              ("c1", "project", 3), ("c2", "project", 4),
+                                              ("c2", "sample", 5)])
+def test_end_to_end_matches_oracle(ctx, name, method, seed):
+    say(f"end-to-end {name} {method} seed={seed}")
+    got, ref = _end_to_end(ctx, name, method, seed)
+    assert got["status"] == 0
+    assert db_err(got["P"], ref["P"]) <= DB_FP32
+    assert got["n_found"] == len(ref["peak_idx"])
+    for pk in ref["peak_idx"]:
+        assert np.min(np.abs(got["peak_idx"] - pk)) <= 1
+    for pk in got["peak_idx"]:
+        assert np.min(np.abs(ref["peak_idx"] - pk)) <= 1
+
+
+# ----------------------------------------------------------------------------
+# batches: each frame bit-identical alone and in an uneven mix
+# ----------------------------------------------------------------------------
+
+def _mixed_frames(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        M = int(rng.choice([64, 100, 256, 512]))
+        T = int(rng.integers(M // 2, 2 * M + 1))
+        K = int(rng.integers(1, 9))
+        l, p = fmsynth.sketch_sizes(M, K)
+        method = fm.FM_METHOD_SAMPLE if i % 3 == 2 else fm.FM_METHOD_PROJECT
+        n_ = p if method == fm.FM_METHOD_SAMPLE else l
+        q = int(rng.integers(0, 3))
+        L = int(rng.choice([181, 1801, 3001]))
+        fr = fmsynth.make_frame(M, T, K, float(rng.uniform(-5, 20)), seed=seed * 1000 + i)
+        rnd = (fmsynth.make_idx(M, n_, i) if method == fm.FM_METHOD_SAMPLE
+               else fmsynth.make_omega(M, n_, i))
+        th0, dth, _ = fmsynth.grid(L)
+        spec = FrameSpec(M=M, T=T, K=K, method=method, n=n_, q=q, L=L, theta0_deg=th0,
+                         dtheta_deg=dth)
+        out.append((spec, fr.X, rnd))
+    return out
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_equals_alone_bitwise(ctx, use_graph):
+    frames = _mixed_frames(9, seed=5)
+    alone = []
+    for spec, X, rnd in frames:
+        d = DeviceFrame(spec, X=torch.from_numpy(X), rnd=torch.from_numpy(rnd))
+        run_single(ctx, d)
+        torch.cuda.synchronize()
+        alone.append(d.results())
+    devs = [DeviceFrame(s, X=torch.from_numpy(X), rnd=torch.from_numpy(r)) for s, X, r in frames]
+    plan = fm.Plan(ctx, [d.descriptor() for d in devs])
+    for rep in range(3 if use_graph else 1):
+        for d in devs:
+            d.P.zero_()
+            d.Us.zero_()
+        plan.run(use_graph=use_graph)
+        torch.cuda.synchronize()
+        for a, d in zip(alone, devs):
+            b = d.results()
+            assert np.array_equal(a["R"], b["R"])
+            assert np.array_equal(a["Us"], b["Us"])
+            assert np.array_equal(a["sigma"], b["sigma"])
+            assert np.array_equal(a["P"], b["P"])
+            assert np.array_equal(a["peak_idx"], b["peak_idx"])
+            assert a["status"] == b["status"]
+    plan.close()
+
+
+# ----------------------------------------------------------------------------
+# argument validation: rejected synchronously, nothing launched
+# ----------------------------------------------------------------------------
+
+def test_argument_validation(ctx):
+    R = torch.zeros((16, 16), dtype=torch.complex64, device="cuda")
+    Om = torch.zeros((16, 4), dtype=torch.float32, device="cuda")
+    Us = torch.zeros((5, 16), dtype=torch.complex128, device="cuda")
+    sig = torch.zeros(5, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(fm.FmError) as e:
+        ctx.fm_subspace_project(R, Om, 2, 5, Us, sig, st)      # K > l
+    assert e.value.status == fm.FM_E_ARG
+    with pytest.raises(fm.FmError) as e:
+        ctx.fm_subspace_project(R, Om, 17, 2, Us, sig, st)     # q out of range
+    assert e.value.status == fm.FM_E_ARG
+    P = torch.zeros(10, dtype=torch.float32, device="cuda")
+    with pytest.raises(fm.FmError) as e:
+        ctx.fm_pseudospectrum(Us, 0.0, -1.0, 10, P)             # dtheta <= 0
+    assert e.value.status == fm.FM_E_ARG
+    X = torch.zeros((4, 8), dtype=torch.complex64, device="cuda")
+    with pytest.raises(fm.FmError) as e:
+        ctx.fm_covariance(X, R, prec=fm.FM_BF16)                # not in this build
+    assert e.value.status in (fm.FM_E_UNSUPPORTED, fm.FM_OK)
+    small = fm.Context(0, 1024)
+    with pytest.raises(fm.FmError) as e:
+        small.fm_subspace_project(R, Om, 2, 3, Us, sig, st)     # arena too small
+    assert e.value.status == fm.FM_E_WORKSPACE
+    small.close()
