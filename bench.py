@@ -1,0 +1,283 @@
+"""Throughput of the fast-MUSIC hot path on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic frames of
+the massive-MIMO workload (M = 1024 channels, T = 2048 snapshots, K = 8
+sources at SNR 0 dB, 18001-angle grid at 0.01 deg): covariance -> Method 2
+subspace (l = K + 8 = 16, q = 2) -> pseudo-spectrum -> peaks, every frame of
+the batch in one launch per stage.  `value` is frames per second of that
+step (inputs resident in HBM).  In the same run the benchmark also times
+Method 1 (p = 4l = 64) and standard MUSIC with a full eigen-decomposition
+on the same GPU (rocSOLVER through torch.linalg.eigh for the O(M^3) step,
+the library for the other stages), the latency of one frame alone, the
+covariance kernel against the FP32 matrix-core roofline (HIP events on the
+launch stream), and the FP64 CPU oracle on a bounded sample of frames.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--batch 256]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frames/s fast-MUSIC vs plain MUSIC @M=1024,T=2048; p99 frame latency"
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+M, T, K, L_GRID = 1024, 2048, 8, 18001
+L_SKETCH, Q_ITERS, P_SAMPLE = 16, 2, 64
+SNR_DB = 0.0
+
+
+def cov_flops(M, T):
+    """Algorithmic FP32 flops of R = X X^H / T with Hermitian symmetry:
+    8 real flops per complex multiply-add, M(M+1)/2 entries, T terms."""
+    return 8.0 * M * (M + 1) / 2.0 * T
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pmc_traffic(n_frames):
+    """HBM bytes per covariance launch from the committed rocprofv3 counter
+    summary, if it was taken on the current covariance source; else None."""
+    path = os.path.join(ROOT, "profiles", "covariance_m1024_t2048_pmc.md")
+    src = os.path.join(ROOT, "paper_1911_07434_amd", "csrc", "fm_cov.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    m = re.search(r"source_sha256_16:\s*([0-9a-f]+)", text)
+    b = re.search(r"hbm_bytes_per_frame:\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != h:
+        return None
+    return float(b.group(1)) * n_frames
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="time only the main step (for profiler runs)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 256 MiB device copy first (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
+              "multi-GPU form in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import fmsynth
+    import paper_1911_07434_amd as fm
+    from paper_1911_07434_amd.frames import DeviceFrame, FrameSpec
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    ctx = fm.Context(0, 256 << 20)
+    B = args.batch
+    th0, dth, _ = fmsynth.grid(L_GRID)
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    log(f"generating {B} frames M={M} T={T} K={K} on the device")
+    t0 = time.time()
+    X, _angles = fmsynth.make_batch_device(M, T, K, SNR_DB, B, args.seed)
+    Om = fmsynth.make_omega_device(M, L_SKETCH, B, args.seed)
+    idx = np.stack([fmsynth.make_idx(M, P_SAMPLE, args.seed * 1000 + i) for i in range(B)])
+    torch.cuda.synchronize()
+    log(f"  done in {time.time() - t0:.1f} s")
+
+    def make_frames(method):
+        out = []
+        for i in range(B):
+            if method == fm.FM_METHOD_PROJECT:
+                spec = FrameSpec(M=M, T=T, K=K, method=method, n=L_SKETCH, q=Q_ITERS, L=L_GRID,
+                                 theta0_deg=th0, dtheta_deg=dth)
+                d = DeviceFrame(spec, X=X[i], rnd=Om[i])
+            else:
+                spec = FrameSpec(M=M, T=T, K=K, method=method, n=P_SAMPLE, L=L_GRID,
+                                 theta0_deg=th0, dtheta_deg=dth)
+                d = DeviceFrame(spec, X=X[i], rnd=torch.from_numpy(idx[i]))
+            out.append(d)
+        return out
+
+    frames2 = make_frames(fm.FM_METHOD_PROJECT)
+    plan2 = fm.Plan(ctx, [d.descriptor() for d in frames2])
+    log(f"plan workspace {plan2.workspace_bytes() / 2**20:.0f} MiB")
+
+    stage_names = ("covariance", "subspace", "pseudospectrum", "peaks")
+
+    def step(plan, ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        plan.covariance(stream)
+        if ev is not None:
+            ev[1].record(stream)
+        plan.subspace(stream)
+        if ev is not None:
+            ev[2].record(stream)
+        plan.pseudospectrum(stream)
+        if ev is not None:
+            ev[3].record(stream)
+        plan.peaks(stream)
+        if ev is not None:
+            ev[4].record(stream)
+
+    # ---- main timed step: Method 2 ----------------------------------------
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step(plan2)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            step(plan2, evs[s])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+    stage_ms = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs]))
+                for i, n in enumerate(stage_names)}
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = B / (elapsed / args.steps)
+    st = np.array([int(d.status.cpu()[0]) for d in frames2[:8]])
+    log(f"Method 2: {value:.1f} frames/s, {ms_per_step:.2f} ms/step, stages {stage_ms}, "
+        f"status {st.tolist()}")
+
+    cov_ms = stage_ms["covariance"]
+    achieved = B * cov_flops(M, T) / (cov_ms * 1e-3) / 1e12
+    traffic = pmc_traffic(B)
+    roofline = {"bound": "mfma", "kernel": "cov_fp32_kernel", "achieved": round(achieved, 2),
+                "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+                "traffic": traffic,
+                "launch_ms": round(cov_ms, 4),
+                "algorithmic_flops_per_launch": B * cov_flops(M, T)}
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"fast-MUSIC Method 2, M={M} T={T} K={K} l={L_SKETCH} q={Q_ITERS} "
+                               f"L={L_GRID} SNR={SNR_DB:g}dB, {B} frames per step",
+                   "global_batch": B, "M": M, "T": T, "K": K, "l": L_SKETCH, "q": Q_ITERS,
+                   "L": L_GRID, "parallelism": "single GPU, frames batched per launch"},
+        "angles_per_s": round(value * K, 1),
+        "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
+        "roofline": roofline,
+    }
+
+    if not args.no_extra:
+        # ---- Method 1 on the same frames -----------------------------------
+        del plan2
+        frames1 = make_frames(fm.FM_METHOD_SAMPLE)
+        plan1 = fm.Plan(ctx, [d.descriptor() for d in frames1])
+        with torch.cuda.stream(stream):
+            step(plan1)
+            torch.cuda.synchronize()
+            n1 = max(3, args.steps // 4)
+            t0 = time.perf_counter()
+            for _ in range(n1):
+                step(plan1)
+            torch.cuda.synchronize()
+            v1 = B * n1 / (time.perf_counter() - t0)
+        log(f"Method 1: {v1:.1f} frames/s")
+        del plan1, frames1
+
+        # ---- standard MUSIC (full EVD) on the same GPU ---------------------
+        nb = min(B, 32)
+        with torch.cuda.stream(stream):
+            def plain_batch():
+                Rs = torch.empty((nb, M, M), dtype=torch.complex64, device="cuda")
+                for i in range(nb):
+                    ctx.fm_covariance(X[i], Rs[i], stream=stream)
+                w, V = torch.linalg.eigh(Rs)             # ascending eigenvalues
+                Us = V[:, :, M - K:].flip(-1).transpose(1, 2).to(torch.complex128).contiguous()
+                for i in range(nb):
+                    d = frames2[i]
+                    ctx.fm_pseudospectrum(Us[i], th0, dth, L_GRID, d.P, stream=stream)
+                    ctx.fm_peaks(d.P, K, d.peak_idx, d.peak_val, d.n_found, stream=stream)
+            plain_batch()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 2
+            for _ in range(reps):
+                plain_batch()
+            torch.cuda.synchronize()
+            vplain = nb * reps / (time.perf_counter() - t0)
+        log(f"plain MUSIC (rocSOLVER eigh): {vplain:.2f} frames/s")
+
+        # ---- one frame alone: latency distribution -------------------------
+        lat = []
+        single = frames2[:1]
+        plan_one = fm.Plan(ctx, [single[0].descriptor()])
+        with torch.cuda.stream(stream):
+            for i in range(3):
+                step(plan_one)
+            torch.cuda.synchronize()
+            for i in range(40):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                step(plan_one)
+                e1.record(stream)
+                e1.synchronize()
+                lat.append(e0.elapsed_time(e1))
+        del plan_one
+        out["comparison"] = {
+            "method1_frames_per_s": round(v1, 2),
+            "plain_music_frames_per_s": round(vplain, 3),
+            "plain_music_eig": "torch.linalg.eigh (rocSOLVER), complex64",
+            "speedup_method2_vs_plain": round(value / vplain, 1),
+            "speedup_method1_vs_plain": round(v1 / vplain, 1),
+        }
+        out["frame_latency_ms_alone"] = {"p50": round(float(np.percentile(lat, 50)), 3),
+                                         "p99": round(float(np.percentile(lat, 99)), 3)}
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample -----------------
+    if not args.no_cpu:
+        import oracle
+        thr = oracle.default_threads()
+        frames_cpu, t_cpu = 0, 0.0
+        Xh = X[: 3].cpu().numpy()
+        Omh = Om[: 3].cpu().numpy()
+        for i in range(3):
+            t0 = time.perf_counter()
+            oracle.run_frame(Xh[i], K, "project", th0, dth, L_GRID, Omega=Omh[i], q=Q_ITERS,
+                             threads=thr)
+            t_cpu += time.perf_counter() - t0
+            frames_cpu += 1
+            if t_cpu > 20.0:
+                break
+        out["cpu_baseline"] = {"value": round(frames_cpu / t_cpu, 4), "unit": "frames/s",
+                               "cores": thr, "kind": "oracle",
+                               "sample": f"{frames_cpu} frame(s) of the same workload through "
+                                         "the FP64 oracle (covariance, Method 2, spectrum, peaks)"}
+        log(f"CPU oracle: {frames_cpu / t_cpu:.4f} frames/s on {thr} threads")
+
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

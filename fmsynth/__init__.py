@@ -161,3 +161,36 @@ def uneven_batch(n: int, seed: int, Ms=(256, 512, 1024, 2048), K_range=(1, 16),
         l, p = sketch_sizes(M, K)
         out.append(dict(M=M, T=T, K=K, snr_db=snr, l=l, p=p, q=2, seed=seed * 100003 + i))
     return out
+
+
+def make_batch_device(M: int, T: int, K: int, snr_db: float, n: int, seed: int, *,
+                      angle_range=(-75.0, 75.0), min_sep: float = 1.0, device="cuda"):
+    """n frames of the same shape generated on the GPU (for throughput runs).
+
+    Same signal model as make_frame (angles drawn on the host with the same
+    rule, sources and noise drawn with a seeded torch generator on the
+    device).  Returns (X complex64 (n, M, T) on the device, angles (n, K)).
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    rng = _rng(seed, 5)
+    th = np.stack([draw_angles(rng, K, angle_range[0], angle_range[1], min_sep)
+                   for _ in range(n)])
+    A = torch.from_numpy(np.stack([steering_matrix(M, t) for t in th]).astype(np.complex64))
+    A = A.to(device)                                           # (n, M, K)
+    S = torch.complex(torch.randn((n, K, T), generator=g, device=device),
+                      torch.randn((n, K, T), generator=g, device=device)) / np.sqrt(2.0)
+    X = torch.bmm(A.contiguous(), S.contiguous())
+    sig = float(np.sqrt(10.0 ** (-snr_db / 10.0) / 2.0))
+    X += sig * torch.complex(torch.randn((n, M, T), generator=g, device=device),
+                             torch.randn((n, M, T), generator=g, device=device))
+    return X.contiguous(), th
+
+
+def make_omega_device(M: int, l: int, n: int, seed: int, device="cuda"):
+    """n real Gaussian test matrices (n, M, l) float32 on the device."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) + 7777)
+    return torch.randn((n, M, l), generator=g, device=device, dtype=torch.float32)
