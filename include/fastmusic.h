@@ -108,8 +108,9 @@ const char *fm_status_string(fm_status s);
 const char *fm_last_error(const fm_ctx *ctx);
 
 /* Arena bytes one single-frame call sequence needs for an M-channel frame
- * with sketch width n (l for Method 2, p for Method 1), K sources. */
-size_t fm_workspace_bytes(int M, int n, int K);
+ * with sketch width n (l for Method 2, p for Method 1), K sources and an
+ * L-angle grid (a plan allocates this much per frame). */
+size_t fm_workspace_bytes(int M, int n, int K, int L);
 
 /* ------------------------------------------------------------------------ */
 /* stage 1: covariance, eqs. (2)-(3)                                        */

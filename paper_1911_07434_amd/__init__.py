@@ -73,7 +73,7 @@ def load_library(path: str = LIB_PATH):
         "fm_destroy": ([P], I),
         "fm_status_string": ([I], C.c_char_p),
         "fm_last_error": ([P], C.c_char_p),
-        "fm_workspace_bytes": ([I, I, I], Z),
+        "fm_workspace_bytes": ([I, I, I, I], Z),
         "fm_covariance": ([P, P, P, I, I, I64, P, I64, I], I),
         "fm_subspace_sample": ([P, P, P, I, I64, P, I, I, D, P, P, P], I),
         "fm_subspace_project": ([P, P, P, I, I64, P, I, I, I, D, I, P, P, P], I),

@@ -49,7 +49,8 @@ struct fm_plan {
 
 namespace {
 
-enum Kind { kCov, kOmega, kGather, kSketch, kGram, kSmall, kApply, kSpec, kPeaks };
+enum Kind { kCov, kOmega, kGather, kSketch, kGram, kSmall, kApply, kSpecPrep, kSpec, kRefine,
+            kPeaks };
 
 fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
   if (ctx) {
@@ -71,10 +72,10 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // per-frame workspace layout (shared by single-frame calls and plans)
 struct WsLayout {
-  size_t y, v, part, small, uf, total;
+  size_t y, v, part, small, uf, rlist, total;
 };
 
-WsLayout ws_layout(int M, int n, int K) {
+WsLayout ws_layout(int M, int n, int K, int L) {
   const int np = (n + 1) & ~1;
   const int nchunk = (M + fm::kGramRows - 1) / fm::kGramRows;
   WsLayout w;
@@ -84,6 +85,7 @@ WsLayout ws_layout(int M, int n, int K) {
   w.part = o;  o += align256((size_t)nchunk * 2 * n * n * 16);
   w.small = o; o += align256(((size_t)fm::kSmallSlots * np * np + 1) * 16);
   w.uf = o;    o += align256((size_t)M * K * 8);
+  w.rlist = o; o += align256((size_t)(L + 1) * 4);
   w.total = o;
   return w;
 }
@@ -94,6 +96,7 @@ void bind_ws(FrameDev &f, char *base, const WsLayout &w) {
   f.part = reinterpret_cast<double2 *>(base + w.part);
   f.small = reinterpret_cast<double2 *>(base + w.small);
   f.Uf = reinterpret_cast<float2 *>(base + w.uf);
+  f.rlist = reinterpret_cast<int *>(base + w.rlist);
   f.nchunk = (f.M + fm::kGramRows - 1) / fm::kGramRows;
   f.npad = (f.n + 1) & ~1;
 }
@@ -204,6 +207,8 @@ hipError_t run_sample_single(FrameDev &f, hipStream_t s) {
   return fm::launch_apply(f, nullptr, nullptr, 0, fm::kApplyUs, s);
 }
 
+int spec_nb(int K) { return (2 * K + 15) / 16; }
+
 int small_class(int n) {
   if (n <= 16) return 16;
   if (n <= 32) return 32;
@@ -230,9 +235,9 @@ FM_API const char *fm_status_string(fm_status s) {
 
 FM_API const char *fm_last_error(const fm_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
 
-FM_API size_t fm_workspace_bytes(int M, int n, int K) {
-  if (M < 1 || n < 1 || K < 0) return 0;
-  return ws_layout(M, n, K).total;
+FM_API size_t fm_workspace_bytes(int M, int n, int K, int L) {
+  if (M < 1 || n < 1 || K < 0 || L < 0) return 0;
+  return ws_layout(M, n, K, L).total;
 }
 
 FM_API fm_status fm_create(int device, size_t workspace_bytes, fm_ctx **out) {
@@ -293,7 +298,7 @@ static fm_status subspace_single(fm_ctx *ctx, void *stream, const void *R, int M
   if (st != FM_OK) return st;
   if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "subspace: bad precision %d", (int)prec);
   if (prec != FM_FP32) return fail(ctx, FM_E_UNSUPPORTED, "subspace: only FM_FP32 in this build");
-  const WsLayout w = ws_layout(M, n, K);
+  const WsLayout w = ws_layout(M, n, K, 0);
   if (w.total > ctx->arena_bytes)
     return fail(ctx, FM_E_WORKSPACE, "subspace: needs %zu arena bytes, have %zu", w.total,
                 ctx->arena_bytes);
@@ -342,7 +347,8 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
   if (st != FM_OK) return st;
   if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "pseudospectrum: bad precision %d", (int)prec);
   if (prec != FM_FP32) return fail(ctx, FM_E_UNSUPPORTED, "pseudospectrum: only FM_FP32 in this build");
-  const size_t need = align256((size_t)M * K * 8);
+  const size_t uf_bytes = align256((size_t)M * K * 8);
+  const size_t need = uf_bytes + align256((size_t)(L + 1) * 4);
   if (need > ctx->arena_bytes)
     return fail(ctx, FM_E_WORKSPACE, "pseudospectrum: needs %zu arena bytes", need);
   if ((st = set_dev(ctx)) != FM_OK) return st;
@@ -351,13 +357,15 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
   f.K = K;
   f.Us = static_cast<double2 *>(const_cast<void *>(Us));
   f.Uf = reinterpret_cast<float2 *>(ctx->arena);
+  f.rlist = reinterpret_cast<int *>(ctx->arena + uf_bytes);
   f.L = L;
   f.theta0 = theta0_deg;
   f.dtheta = dtheta_deg;
   f.P = P;
   hipStream_t s = (hipStream_t)stream;
   FM_CHECK_LAUNCH(ctx, fm::launch_uf(f, s));
-  FM_CHECK_LAUNCH(ctx, fm::launch_spectrum(f, nullptr, nullptr, 0, prec, s));
+  FM_CHECK_LAUNCH(ctx, fm::launch_spectrum(f, nullptr, nullptr, 0, spec_nb(K), prec, s));
+  FM_CHECK_LAUNCH(ctx, fm::launch_refine(f, nullptr, nullptr, 0, s));
   return FM_OK;
 }
 
@@ -398,7 +406,9 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kGram: return fm::launch_gram(cls, fr, it, L.count, L.mode, s);
     case kSmall: return fm::launch_small(cls, fr, it, L.count, L.mode, s);
     case kApply: return fm::launch_apply(cls, fr, it, L.count, L.mode, s);
-    case kSpec: return fm::launch_spectrum(cls, fr, it, L.count, p->prec, s);
+    case kSpecPrep: return fm::launch_spec_prep(fr, it, L.count, s);
+    case kSpec: return fm::launch_spectrum(cls, fr, it, L.count, L.n_class, p->prec, s);
+    case kRefine: return fm::launch_refine(cls, fr, it, L.count, s);
     case kPeaks: return fm::launch_peaks(cls, fr, it, L.count, s);
   }
   return hipErrorInvalidValue;
@@ -448,7 +458,7 @@ FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frame
   std::vector<size_t> off(n_frames);
   size_t total = 0;
   for (int i = 0; i < n_frames; ++i) {
-    lay[i] = ws_layout(frames[i].M, frames[i].n, frames[i].K);
+    lay[i] = ws_layout(frames[i].M, frames[i].n, frames[i].K, frames[i].L);
     off[i] = total;
     total += lay[i].total;
   }
@@ -579,9 +589,19 @@ FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frame
   add(p->sub, kApply, fm::kApplyUs, 0, b0);
 
   b0 = begin();
+  for (int i : order) items.push_back({i, 0, 0, 0});
+  add(p->spec, kSpecPrep, 0, 0, b0);
+  for (int nb = 1; nb <= 8; ++nb) {
+    b0 = begin();
+    for (int i : order)
+      if (spec_nb(frames[i].K) == nb)
+        for (int t = 0; t < rows(frames[i].L, fm::kSpecAngles); ++t) items.push_back({i, t, 0, 0});
+    add(p->spec, kSpec, 0, nb, b0);
+  }
+  b0 = begin();
   for (int i : order)
-    for (int t = 0; t < rows(frames[i].L, fm::kSpecAngles); ++t) items.push_back({i, t, 0, 0});
-  add(p->spec, kSpec, 0, 0, b0);
+    for (int g = 0; g < fm::kRefineGroups; ++g) items.push_back({i, g, 0, 0});
+  add(p->spec, kRefine, 0, 0, b0);
   b0 = begin();
   for (int i : order) items.push_back({i, 0, 0, 0});
   add(p->peaks, kPeaks, 0, 0, b0);

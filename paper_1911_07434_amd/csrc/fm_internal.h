@@ -41,6 +41,7 @@ struct FrameDev {
   double2 *part;        // [nchunk][2][n][n] Gram partial sums
   double2 *small;       // small dense scratch, kSmallSlots * npad^2
   float2 *Uf;           // [M][K] FP32 copy of U_s for the FP32 spectrum pass
+  int *rlist;           // [1 + L]: count, then angles whose FP32 denominator needs FP64
   int nchunk;           // ceil(M / kGramRows)
   int npad;             // n rounded up to even
 };
@@ -56,6 +57,8 @@ constexpr int kCovTile = 128;      // covariance tile edge (complex entries)
 constexpr int kSketchRows = 128;   // rows of R per sketch workgroup
 constexpr int kApplyRows = 64;     // rows per apply / gather workgroup
 constexpr int kSpecAngles = 64;    // angles per spectrum workgroup
+constexpr int kSpecChunk = 64;     // channels of U_s staged in LDS per step
+constexpr int kRefineGroups = 4;   // FP64 recompute workgroups per frame
 constexpr int kMaxL = 64;          // max sketch width of Method 2 (l)
 constexpr int kMaxN = 256;         // max sketch width of Method 1 (p)
 constexpr int kMaxK = 64;          // max number of sources
@@ -88,8 +91,16 @@ hipError_t launch_small(const FrameDev &single, const FrameDev *frames, const It
 hipError_t launch_apply(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, int mode, hipStream_t s);
 hipError_t launch_uf(const FrameDev &single, hipStream_t s);
+// spectrum stage = prep (reset the recompute lists; batched only -- the
+// single-frame path resets it in launch_uf), the FP32 pass (one launch per
+// row-block class nb = ceil(2K/16), passed in single.K for batched launches)
+// and the FP64 recompute of the listed angles
+hipError_t launch_spec_prep(const FrameDev *frames, const Item *items, int n_items,
+                            hipStream_t s);
 hipError_t launch_spectrum(const FrameDev &single, const FrameDev *frames, const Item *items,
-                           int n_items, fm_prec prec, hipStream_t s);
+                           int n_items, int nb, fm_prec prec, hipStream_t s);
+hipError_t launch_refine(const FrameDev &single, const FrameDev *frames, const Item *items,
+                         int n_items, hipStream_t s);
 hipError_t launch_peaks(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, hipStream_t s);
 

@@ -19,8 +19,9 @@
 // to the exact phasor every 64 channels.
 //
 // Every angle whose FP32 denominator is below M/16 (the cancellation-prone
-// main lobes) is recomputed in FP64 from the FP64 U_s by the wave that owns
-// it; a denominator below M*2^-53 is clamped (noiseless on-grid pole).
+// main lobes) is appended to a per-frame list, and a second kernel
+// recomputes those angles in FP64 from the FP64 U_s (one wave per angle);
+// a denominator below M*2^-53 is clamped there (noiseless on-grid pole).
 #include "fm_internal.h"
 
 namespace fm {
@@ -80,7 +81,9 @@ __device__ __forceinline__ const FrameDev &spec_frame(const FrameDev &single,
   }
 }
 
-// FP64 denominator of one angle, computed by the whole wave
+// FP64 denominator of one angle, computed by the whole wave: each lane
+// walks every 64th channel with an FP64 phasor recurrence (64 steps at most
+// per exact start, error ~1e-14), K accumulated 16 at a time.
 __device__ double den_fp64(const FrameDev &f, unsigned long long F, int lane) {
   const int M = f.M, K = f.K;
   double proj = 0.0;
@@ -117,15 +120,20 @@ __device__ double den_fp64(const FrameDev &f, unsigned long long F, int lane) {
   return (double)M - proj;
 }
 
+// FP32 pass over one tile of kSpecAngles angles (four waves of 16).  U_s is
+// staged through LDS in chunks of kSpecChunk channels, double buffered: the
+// next chunk's global loads are in flight while the matrix cores work on
+// the current one.  NB = row blocks of 16 over the 2K stacked outputs.
 template <int NB>
-__device__ __forceinline__ void spectrum_tile(const FrameDev &f, int tile, const float2 *tab) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+__device__ __forceinline__ void spectrum_tile(const FrameDev &f, int tile, const float2 *tab,
+                                              float2 (*ubuf)[kSpecChunk * 8 * NB]) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int n = lane & 15, r = lane >> 4;
   const int M = f.M, K = f.K, L = f.L;
   const int gl = tile * kSpecAngles + wave * 16 + n;
   const unsigned long long F = turn_freq(f.theta0, f.dtheta, min(gl, L - 1));
-  const float2 w4 = phasor32(4u, F, tab);
 
   int kk[NB], part[NB];
   bool okr[NB];
@@ -140,19 +148,51 @@ __device__ __forceinline__ void spectrum_tile(const FrameDev &f, int tile, const
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  float2 ph = make_float2(1.f, 0.f);
-  for (int m0 = 0; m0 < M; m0 += 4) {
-    const int m = m0 + r;
-    ph = ((m0 & 63) == 0) ? phasor32((unsigned)m, F, tab) : cmulf(ph, w4);
-    const bool okm = m < M;
+  // cooperative chunk loads: kSpecChunk * K float2, at most 2 * NB per thread
+  const int chunk_elems = kSpecChunk * K;
+  const int nchunk = (M + kSpecChunk - 1) / kSpecChunk;
+  const size_t total = (size_t)M * K;
+  float2 stage[2 * NB];
+  auto load_chunk = [&](int c) {
+    const size_t base = (size_t)c * chunk_elems;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const float2 u = (okm && okr[b]) ? f.Uf[(size_t)m * K + kk[b]] : make_float2(0.f, 0.f);
-      const float a1 = part[b] == 0 ? u.x : -u.y;
-      const float a2 = part[b] == 0 ? u.y : u.x;
-      acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, ph.x, acc[b], 0, 0, 0);
-      acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, ph.y, acc[b], 0, 0, 0);
+    for (int j = 0; j < 2 * NB; ++j) {
+      const int e = tid + 256 * j;
+      stage[j] = (e < chunk_elems && base + e < total) ? f.Uf[base + e] : make_float2(0.f, 0.f);
     }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 2 * NB; ++j) {
+      const int e = tid + 256 * j;
+      if (e < chunk_elems) ubuf[buf][e] = stage[j];
+    }
+  };
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();  // publishes the first chunk and the phasor table
+  const float2 w4 = phasor32(4u, F, tab);
+
+  float2 ph = make_float2(1.f, 0.f);
+  for (int c = 0; c < nchunk; ++c) {
+    const bool more = c + 1 < nchunk;
+    if (more) load_chunk(c + 1);
+    const float2 *ub = ubuf[c & 1];
+#pragma unroll 4
+    for (int s = 0; s < kSpecChunk / 4; ++s) {
+      const int m = c * kSpecChunk + 4 * s + r;
+      ph = (s == 0) ? phasor32((unsigned)m, F, tab) : cmulf(ph, w4);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float2 u = okr[b] ? ub[(4 * s + r) * K + kk[b]] : make_float2(0.f, 0.f);
+        const float a1 = part[b] == 0 ? u.x : -u.y;
+        const float a2 = part[b] == 0 ? u.y : u.x;
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, ph.x, acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, ph.y, acc[b], 0, 0, 0);
+      }
+    }
+    if (more) store_chunk((c + 1) & 1);
+    __syncthreads();
   }
   float ss = 0.f;
 #pragma unroll
@@ -161,59 +201,83 @@ __device__ __forceinline__ void spectrum_tile(const FrameDev &f, int tile, const
     for (int v = 0; v < 4; ++v) ss = fmaf(acc[b][v], acc[b][v], ss);
   ss += __shfl_xor(ss, 16);
   ss += __shfl_xor(ss, 32);
-  const float den32 = (float)M - ss;
-  const float floor32 = (float)M * 5.9604644775390625e-08f;  // M * 2^-24
-  float pval = 1.0f / fmaxf(den32, floor32);
-
-  // FP64 recompute of the cancellation-prone angles
-  const bool flag = (r == 0) && (gl < L) && (den32 < (float)M * 0.0625f);
-  unsigned long long mask = __ballot(flag);
-  while (mask) {
-    const int j = __ffsll((long long)mask) - 1;
-    mask &= mask - 1;
-    const int glj = tile * kSpecAngles + wave * 16 + j;
-    const unsigned long long Fj = turn_freq(f.theta0, f.dtheta, glj);
-    const double d = den_fp64(f, Fj, lane);
-    const double floor64 = (double)M * 1.1102230246251565e-16;  // M * 2^-53
-    if (lane == j) pval = (float)(1.0 / fmax(d, floor64));
+  if (r == 0 && gl < L) {
+    const float den32 = (float)M - ss;
+    const float floor32 = (float)M * 5.9604644775390625e-08f;  // M * 2^-24
+    f.P[gl] = 1.0f / fmaxf(den32, floor32);
+    // main lobes, where M - ||U^H a||^2 cancels, are recomputed in FP64
+    if (den32 < (float)M * 0.0625f) {
+      const int slot = atomicAdd(f.rlist, 1);
+      f.rlist[1 + slot] = gl;
+    }
   }
-  if (r == 0 && gl < L) f.P[gl] = pval;
 }
 
-template <bool kBatched>
+template <int NB, bool kBatched>
 __global__ __launch_bounds__(256) void spectrum_kernel(FrameDev single, const FrameDev *frames,
                                                        const Item *items) {
   __shared__ float2 tab[256];
+  __shared__ float2 ubuf[2][kSpecChunk * 8 * NB];
   {
     double s, c;
     sincospi((double)threadIdx.x / 128.0, &s, &c);
     tab[threadIdx.x] = make_float2((float)c, (float)s);
   }
-  __syncthreads();
+  // (the first __syncthreads in spectrum_tile also publishes the table)
   int tile;
   const FrameDev &f = spec_frame<kBatched>(single, frames, items, tile);
-  const int nb = (2 * f.K + 15) / 16;
-  switch (nb) {
-    case 1: spectrum_tile<1>(f, tile, tab); break;
-    case 2: spectrum_tile<2>(f, tile, tab); break;
-    case 3: spectrum_tile<3>(f, tile, tab); break;
-    case 4: spectrum_tile<4>(f, tile, tab); break;
-    case 5: spectrum_tile<5>(f, tile, tab); break;
-    case 6: spectrum_tile<6>(f, tile, tab); break;
-    case 7: spectrum_tile<7>(f, tile, tab); break;
-    default: spectrum_tile<8>(f, tile, tab); break;
+  spectrum_tile<NB>(f, tile, tab, ubuf);
+}
+
+// FP64 recompute of the listed angles: one wave per angle, the frame's
+// kRefineGroups workgroups striding over its list
+template <bool kBatched>
+__global__ __launch_bounds__(256) void refine_kernel(FrameDev single, const FrameDev *frames,
+                                                     const Item *items) {
+  int part;
+  const FrameDev &f = spec_frame<kBatched>(single, frames, items, part);
+  const int lane = threadIdx.x & 63;
+  const int gw = part * 4 + (threadIdx.x >> 6);
+  const int cnt = f.rlist[0];
+  const double floor64 = (double)f.M * 1.1102230246251565e-16;  // M * 2^-53
+  for (int e = gw; e < cnt; e += kRefineGroups * 4) {
+    const int gl = f.rlist[1 + e];
+    const unsigned long long F = turn_freq(f.theta0, f.dtheta, gl);
+    const double d = den_fp64(f, F, lane);
+    if (lane == 0) f.P[gl] = (float)(1.0 / fmax(d, floor64));
   }
 }
 
+// reset the recompute lists of the frames of a plan
+__global__ void spec_prep_kernel(const FrameDev *frames, const Item *items, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) frames[items[i].frame].rlist[0] = 0;
+}
+
 // FP32 copy of U_s, transposed to [M][K] so that one channel's K entries are
-// contiguous for the MFMA operand loads
+// contiguous for the MFMA operand loads; also resets the recompute list
 __global__ __launch_bounds__(256) void uf_kernel(FrameDev f) {
   const int M = f.M, K = f.K;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) f.rlist[0] = 0;
   if (e >= M * K) return;
   const int m = e / K, k = e % K;
   const double2 u = f.Us[(size_t)k * M + m];
   f.Uf[e] = make_float2((float)u.x, (float)u.y);
+}
+
+template <int NB>
+hipError_t launch_nb(const FrameDev &single, const FrameDev *frames, const Item *items,
+                     int n_items, hipStream_t s) {
+  if (items) {
+    hipLaunchKernelGGL((spectrum_kernel<NB, true>), dim3(n_items), dim3(256), 0, s, single,
+                       frames, items);
+  } else {
+    const int tiles = (single.L + kSpecAngles - 1) / kSpecAngles;
+    hipLaunchKernelGGL((spectrum_kernel<NB, false>), dim3(tiles), dim3(256), 0, s, single,
+                       frames, items);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -224,17 +288,36 @@ hipError_t launch_uf(const FrameDev &single, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_spec_prep(const FrameDev *frames, const Item *items, int n_items,
+                            hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(spec_prep_kernel, dim3((n_items + 255) / 256), dim3(256), 0, s, frames,
+                     items, n_items);
+  return hipGetLastError();
+}
+
 hipError_t launch_spectrum(const FrameDev &single, const FrameDev *frames, const Item *items,
-                           int n_items, fm_prec prec, hipStream_t s) {
+                           int n_items, int nb, fm_prec prec, hipStream_t s) {
   (void)prec;
-  if (items) {
-    hipLaunchKernelGGL(spectrum_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames,
-                       items);
-  } else {
-    const int tiles = (single.L + kSpecAngles - 1) / kSpecAngles;
-    hipLaunchKernelGGL(spectrum_kernel<false>, dim3(tiles), dim3(256), 0, s, single, frames,
-                       items);
+  switch (nb) {
+    case 1: return launch_nb<1>(single, frames, items, n_items, s);
+    case 2: return launch_nb<2>(single, frames, items, n_items, s);
+    case 3: return launch_nb<3>(single, frames, items, n_items, s);
+    case 4: return launch_nb<4>(single, frames, items, n_items, s);
+    case 5: return launch_nb<5>(single, frames, items, n_items, s);
+    case 6: return launch_nb<6>(single, frames, items, n_items, s);
+    case 7: return launch_nb<7>(single, frames, items, n_items, s);
+    default: return launch_nb<8>(single, frames, items, n_items, s);
   }
+}
+
+hipError_t launch_refine(const FrameDev &single, const FrameDev *frames, const Item *items,
+                         int n_items, hipStream_t s) {
+  if (items)
+    hipLaunchKernelGGL(refine_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames, items);
+  else
+    hipLaunchKernelGGL(refine_kernel<false>, dim3(kRefineGroups), dim3(256), 0, s, single, frames,
+                       items);
   return hipGetLastError();
 }
 

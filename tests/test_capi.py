@@ -47,10 +47,10 @@ def test_status_strings(lib):
 
 
 def test_workspace_bytes_grows_with_shape(lib):
-    a = lib.fm_workspace_bytes(1024, 16, 8)
-    b = lib.fm_workspace_bytes(4096, 24, 16)
+    a = lib.fm_workspace_bytes(1024, 16, 8, 18001)
+    b = lib.fm_workspace_bytes(4096, 24, 16, 36001)
     assert 0 < a < b
-    assert lib.fm_workspace_bytes(0, 16, 8) == 0
+    assert lib.fm_workspace_bytes(0, 16, 8, 100) == 0
     assert a % 256 == 0
 
 
