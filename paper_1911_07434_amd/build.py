@@ -27,6 +27,9 @@ ARCH = "gfx950"
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep MFMA accumulators in ordinary VGPRs: the AGPR form made the
+    # covariance loop copy every accumulator through v_accvgpr_read each step
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 

@@ -172,6 +172,10 @@ fm_status check_peaks(fm_ctx *c, const void *P, int L, int K, const void *idx, c
   return FM_OK;
 }
 
+// MFMA row/column block classes (one kernel instantiation per class)
+int spec_nb(int K) { return (2 * K + 15) / 16; }
+int sketch_nb(int n) { return (2 * n + 31) / 32; }
+
 // ---------------------------------------------------------------------------
 // single-frame stage-2 sequences (identical kernels to the batched plan)
 // ---------------------------------------------------------------------------
@@ -186,12 +190,12 @@ hipError_t run_project_single(FrameDev &f, hipStream_t s, fm_prec prec) {
   if ((e = fm::launch_omega(f, nullptr, nullptr, 0, 0, s)) != hipSuccess) return e;
   if (f.q == 0) {
     if ((e = orth()) != hipSuccess) return e;
-    if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, prec, s)) != hipSuccess) return e;
+    if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, sketch_nb(f.n), prec, s)) != hipSuccess) return e;
   } else {
-    if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, prec, s)) != hipSuccess) return e;
+    if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, sketch_nb(f.n), prec, s)) != hipSuccess) return e;
     for (int i = 0; i < f.q; ++i) {
       if ((e = orth()) != hipSuccess) return e;
-      if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, prec, s)) != hipSuccess) return e;
+      if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, sketch_nb(f.n), prec, s)) != hipSuccess) return e;
     }
   }
   if ((e = fm::launch_gram(f, nullptr, nullptr, 0, fm::kGramFinal, s)) != hipSuccess) return e;
@@ -207,7 +211,6 @@ hipError_t run_sample_single(FrameDev &f, hipStream_t s) {
   return fm::launch_apply(f, nullptr, nullptr, 0, fm::kApplyUs, s);
 }
 
-int spec_nb(int K) { return (2 * K + 15) / 16; }
 
 int small_class(int n) {
   if (n <= 16) return 16;
@@ -402,7 +405,7 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kCov: return fm::launch_covariance(cls, fr, it, L.count, p->prec, s);
     case kOmega: return fm::launch_omega(cls, fr, it, L.count, 0, s);
     case kGather: return fm::launch_gather(cls, fr, it, L.count, s);
-    case kSketch: return fm::launch_sketch(cls, fr, it, L.count, p->prec, s);
+    case kSketch: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, p->prec, s);
     case kGram: return fm::launch_gram(cls, fr, it, L.count, L.mode, s);
     case kSmall: return fm::launch_small(cls, fr, it, L.count, L.mode, s);
     case kApply: return fm::launch_apply(cls, fr, it, L.count, L.mode, s);
@@ -555,11 +558,14 @@ FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frame
     add(p->sub, kApply, fm::kApplyV, 0, b);
   };
   auto sketch_round = [&](auto pred) {
-    size_t b = begin();
-    for (int i : order)
-      if (pred(i))
-        for (int c = 0; c < rows(frames[i].M, fm::kSketchRows); ++c) items.push_back({i, c, 0, 0});
-    add(p->sub, kSketch, 0, 0, b);
+    for (int nb = 1; nb <= 4; ++nb) {
+      size_t b = begin();
+      for (int i : order)
+        if (pred(i) && sketch_nb(frames[i].n) == nb)
+          for (int c = 0; c < rows(frames[i].M, fm::kSketchRows); ++c)
+            items.push_back({i, c, 0, 0});
+      add(p->sub, kSketch, 0, nb, b);
+    }
   };
   int qmax = 0;
   for (int i = 0; i < n_frames; ++i)

@@ -59,6 +59,22 @@ __device__ __forceinline__ void cov_step(CovAcc &acc, const float2 (&a)[2][4],
   }
 }
 
+// global-address-space view of a frame pointer (FrameDev holds generic
+// pointers; global loads avoid the flat path's shared counters)
+typedef FM_GLOBAL const float2 gfloat2;
+
+__device__ __forceinline__ void load8(float2 (&a)[2][4], float2 (&b)[2][4],
+                                      const gfloat2 *const (&pa)[2],
+                                      const gfloat2 *const (&pb)[2], int t) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      a[q][s] = pa[q][t + s];
+      b[q][s] = pb[q][t + s];
+    }
+}
+
 __device__ __forceinline__ void cov_tile(const FrameDev &f, int ti, int tj) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -71,13 +87,13 @@ __device__ __forceinline__ void cov_tile(const FrameDev &f, int ti, int tj) {
   const int jb = tj * kCovTile + wj * 64;
   // rows past M are clamped to a valid row: they only feed outputs that are
   // never stored
-  const float2 *pa[2], *pb[2];
+  const gfloat2 *pa[2], *pb[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    int ia = min(ib + 32 * q + r, M - 1);
-    int ja = min(jb + 32 * q + r, M - 1);
-    pa[q] = f.X + (size_t)ia * f.ldx + 4 * h;
-    pb[q] = f.X + (size_t)ja * f.ldx + 4 * h;
+    const int ia = min(ib + 32 * q + r, M - 1);
+    const int ja = min(jb + 32 * q + r, M - 1);
+    pa[q] = (const gfloat2 *)(f.X + (size_t)ia * f.ldx + 4 * h);
+    pb[q] = (const gfloat2 *)(f.X + (size_t)ja * f.ldx + 4 * h);
   }
   CovAcc acc;
 #pragma unroll
@@ -90,49 +106,36 @@ __device__ __forceinline__ void cov_tile(const FrameDev &f, int ti, int tj) {
         acc.im[bi][bj][v] = 0.f;
       }
 
-  const int Tfull = T & ~7;
-  float2 a[2][4], b[2][4];
-  if (Tfull > 0) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        a[q][s] = pa[q][s];
-        b[q][s] = pb[q][s];
-      }
-  }
-  for (int t = 0; t < Tfull; t += 8) {
-    float2 an[2][4], bn[2][4];
-    const bool more = (t + 8) < Tfull;
-    if (more) {
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          an[q][s] = pa[q][t + 8 + s];
-          bn[q][s] = pb[q][t + 8 + s];
-        }
-    }
-    cov_step(acc, a, b);
-    if (more) {
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          a[q][s] = an[q][s];
-          b[q][s] = bn[q][s];
-        }
+  // full chunks of 8 snapshots, two register buffers in ping-pong; the
+  // prefetch address is clamped to the last full chunk so every load is
+  // valid and no register copies are needed
+  const int nfull = T >> 3;
+  if (nfull > 0) {
+    const int tlast = (nfull - 1) * 8;
+    float2 a0[2][4], b0[2][4], a1[2][4], b1[2][4];
+    load8(a0, b0, pa, pb, 0);
+    for (int c = 0; c < nfull; c += 2) {
+      load8(a1, b1, pa, pb, min((c + 1) * 8, tlast));
+      cov_step(acc, a0, b0);
+      load8(a0, b0, pa, pb, min((c + 2) * 8, tlast));
+      if (c + 1 < nfull) cov_step(acc, a1, b1);
     }
   }
+  const int Tfull = nfull * 8;
   if (Tfull < T) {
     // ragged tail: snapshots past T contribute zero
+    float2 a[2][4], b[2][4];
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const bool ok = (Tfull + 4 * h + s) < T;
-        a[q][s] = ok ? pa[q][Tfull + s] : make_float2(0.f, 0.f);
-        b[q][s] = ok ? pb[q][Tfull + s] : make_float2(0.f, 0.f);
+        a[q][s] = make_float2(0.f, 0.f);
+        b[q][s] = make_float2(0.f, 0.f);
+        if (ok) {
+          a[q][s] = pa[q][Tfull + s];
+          b[q][s] = pb[q][Tfull + s];
+        }
       }
     cov_step(acc, a, b);
   }

@@ -8,6 +8,14 @@
 
 #include "fastmusic.h"
 
+// Global address space for device-side loads through FrameDev's generic
+// pointers (global_load instead of flat_load); host passes see a plain type.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FM_GLOBAL __attribute__((address_space(1)))
+#else
+#define FM_GLOBAL
+#endif
+
 namespace fm {
 
 // Everything one frame needs on the device: caller buffers (inputs and
@@ -80,8 +88,9 @@ hipError_t launch_covariance(const FrameDev &single, const FrameDev *frames,
                              const Item *items, int n_items, fm_prec prec, hipStream_t s);
 hipError_t launch_omega(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, int to_y, hipStream_t s);
+// nb = ceil(2n / 32): MFMA column blocks of the sketch (one launch per class)
 hipError_t launch_sketch(const FrameDev &single, const FrameDev *frames, const Item *items,
-                         int n_items, fm_prec prec, hipStream_t s);
+                         int n_items, int nb, fm_prec prec, hipStream_t s);
 hipError_t launch_gather(const FrameDev &single, const FrameDev *frames, const Item *items,
                          int n_items, hipStream_t s);
 hipError_t launch_gram(const FrameDev &single, const FrameDev *frames, const Item *items,

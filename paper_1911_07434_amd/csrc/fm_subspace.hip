@@ -89,17 +89,27 @@ __global__ __launch_bounds__(256) void omega_kernel(FrameDev single, const Frame
 // sketch: Y = R V on FP32 MFMA.  One wave = 32 rows of R, all 2n real output
 // columns (n real parts, then n imaginary parts) in NB blocks of 32:
 //   Re Y = Rr Vr - Ri Vi,  Im Y = Rr Vi + Ri Vr
-// Each lane owns 4 consecutive elements of its row per step (the two
-// half-waves cover 8 consecutive columns of R), which is both the MFMA K
-// index and a contiguous 32-byte load.
+// R streams in chunks of 32 columns: each lane owns 16 consecutive elements
+// of its row (half-wave h covers columns 16h..16h+15 of the chunk), prefetched
+// one chunk ahead in ping-pong registers; the chunk of V (32 x n) is staged
+// once per workgroup in double-buffered LDS.  MFMA step s pairs column s of
+// the first half with column 16+s of the second.
 // ---------------------------------------------------------------------------
-template <int NB>
-__device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0) {
-  const int lane = threadIdx.x & 63;
+constexpr int kSkChunkMax = 32;
+typedef FM_GLOBAL const float2 gfloat2;
+
+// SK = elements of its row each lane holds per chunk (chunk = 2 SK columns);
+// wide column classes use SK = 8 to stay within the register file
+template <int NB, int SK>
+__device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0,
+                                            float2 (*vbuf)[kSkChunkMax * kMaxL]) {
+  constexpr int kSkChunk = 2 * SK;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
   const int r = lane & 31, h = lane >> 5;
   const int M = f.M, n = f.n;
   const int row = min(i0 + r, M - 1);
-  const float2 *pr = f.R + (size_t)row * f.ldr + 4 * h;
+  const gfloat2 *pr = (const gfloat2 *)(f.R + (size_t)row * f.ldr + SK * h);
   int col[NB], part[NB];
   bool okc[NB];
 #pragma unroll
@@ -115,15 +125,46 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
 
-  const float2 *V = f.V;
-  auto step = [&](const float2 (&a)[4], int mb, int mlim) {
+  const int nchunk = (M + kSkChunk - 1) / kSkChunk;
+  const int velems = kSkChunk * n;  // <= 32 * 64 = 2048 -> at most 8 per thread
+  const gfloat2 *V = (const gfloat2 *)f.V;
+  float2 vst[8];
+  auto load_v = [&](int c) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int m = mb + 4 * h + s;
-      const bool okm = m < mlim;
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      const int m = c * kSkChunk + e / n;
+      vst[j] = make_float2(0.f, 0.f);
+      if (e < velems && m < M) vst[j] = V[(size_t)c * kSkChunk * n + e];
+    }
+  };
+  auto store_v = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      if (e < velems) vbuf[buf][e] = vst[j];
+    }
+  };
+  // R chunk c: SK elements of this lane's row; columns past M read as zero
+  auto load_r = [&](float2 (&a)[SK], int c) {
+    const int m0 = c * kSkChunk + SK * h;
+    if (m0 + SK <= M) {
+#pragma unroll
+      for (int s = 0; s < SK; ++s) a[s] = pr[c * kSkChunk + s];
+    } else {
+#pragma unroll
+      for (int s = 0; s < SK; ++s) {
+        a[s] = make_float2(0.f, 0.f);
+        if (m0 + s < M) a[s] = pr[c * kSkChunk + s];
+      }
+    }
+  };
+  auto compute = [&](const float2 (&a)[SK], const float2 *vb) {
+#pragma unroll
+    for (int s = 0; s < SK; ++s) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        float2 v = (okm && okc[b]) ? V[(size_t)m * n + col[b]] : make_float2(0.f, 0.f);
+        const float2 v = okc[b] ? vb[(SK * h + s) * n + col[b]] : make_float2(0.f, 0.f);
         const float bre = part[b] == 0 ? v.x : v.y;
         const float bim = part[b] == 0 ? -v.y : v.x;
         acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s].x, bre, acc[b], 0, 0, 0);
@@ -131,19 +172,31 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0) {
       }
     }
   };
-  const int Mfull = M & ~7;
-  for (int m0 = 0; m0 < Mfull; m0 += 8) {
-    float2 a[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) a[s] = pr[m0 + s];
-    step(a, m0, M);
-  }
-  if (Mfull < M) {
-    float2 a[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-      a[s] = (Mfull + 4 * h + s < M) ? pr[Mfull + s] : make_float2(0.f, 0.f);
-    step(a, Mfull, M);
+
+  float2 a0[SK], a1[SK];
+  load_v(0);
+  store_v(0);
+  load_r(a0, 0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; c += 2) {
+    // chunk c from (a0, vbuf[0]); chunk c+1 from (a1, vbuf[1])
+    const bool has1 = c + 1 < nchunk;
+    if (has1) {
+      load_v(c + 1);
+      load_r(a1, c + 1);
+    }
+    compute(a0, vbuf[0]);
+    if (has1) store_v(1);
+    __syncthreads();
+    if (!has1) break;
+    const bool has2 = c + 2 < nchunk;
+    if (has2) {
+      load_v(c + 2);
+      load_r(a0, c + 2);
+    }
+    compute(a1, vbuf[1]);
+    if (has2) store_v(0);
+    __syncthreads();
   }
   float *Yf = reinterpret_cast<float *>(f.Y);
 #pragma unroll
@@ -157,20 +210,19 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0) {
   }
 }
 
-template <bool kBatched>
+// one instantiation per NB = ceil(2n / 32); a launch only holds frames of one
+// class (the plan groups them), so no kernel carries the registers of a
+// wider class
+template <int NB, bool kBatched>
 __global__ __launch_bounds__(256) void sketch_kernel(FrameDev single, const FrameDev *frames,
                                                      const Item *items) {
+  __shared__ float2 vbuf[2][kSkChunkMax * kMaxL];
   int blk, unused;
   const FrameDev &f = frame_of<kBatched>(single, frames, items, blk, unused);
+  // every wave takes part in the V staging and the barriers; waves whose
+  // rows start past M clamp to row M-1 and store nothing
   const int i0 = blk * kSketchRows + (threadIdx.x >> 6) * 32;
-  if (i0 >= f.M) return;
-  const int nb = (2 * f.n + 31) / 32;
-  switch (nb) {
-    case 1: sketch_rows<1>(f, i0); break;
-    case 2: sketch_rows<2>(f, i0); break;
-    case 3: sketch_rows<3>(f, i0); break;
-    default: sketch_rows<4>(f, i0); break;
-  }
+  sketch_rows<NB, (NB <= 2 ? 16 : 8)>(f, i0, vbuf);
 }
 
 // ---------------------------------------------------------------------------
@@ -655,11 +707,19 @@ hipError_t launch_omega(const FrameDev &single, const FrameDev *frames, const It
 }
 
 hipError_t launch_sketch(const FrameDev &single, const FrameDev *frames, const Item *items,
-                         int n_items, fm_prec prec, hipStream_t s) {
+                         int n_items, int nb, fm_prec prec, hipStream_t s) {
   (void)prec;
-  const int per = (single.M + kSketchRows - 1) / kSketchRows;
-  if (items) hipLaunchKernelGGL(sketch_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames, items);
-  else hipLaunchKernelGGL(sketch_kernel<false>, dim3(per), dim3(256), 0, s, single, frames, items);
+  const dim3 g(items ? n_items : (single.M + kSketchRows - 1) / kSketchRows), b(256);
+#define FM_SK(NB)                                                                            \
+  if (items) hipLaunchKernelGGL((sketch_kernel<NB, true>), g, b, 0, s, single, frames, items); \
+  else hipLaunchKernelGGL((sketch_kernel<NB, false>), g, b, 0, s, single, frames, items);
+  switch (nb) {
+    case 1: FM_SK(1); break;
+    case 2: FM_SK(2); break;
+    case 3: FM_SK(3); break;
+    default: FM_SK(4); break;
+  }
+#undef FM_SK
   return hipGetLastError();
 }
 
