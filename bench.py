@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "frames/s fast-MUSIC vs plain MUSIC @M=1024,T=2048; p99 frame latency"
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_F16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 M, T, K, L_GRID = 1024, 2048, 8, 18001
 L_SKETCH, Q_ITERS, P_SAMPLE = 16, 2, 64
@@ -189,6 +190,35 @@ def main():
     }
 
     if not args.no_extra:
+        # ---- mixed precision: 16-bit covariance operands, same frames ------
+        mixed = {}
+        for pname, prec in (("fp16", fm.FM_FP16), ("bf16", fm.FM_BF16)):
+            planm = fm.Plan(ctx, [d.descriptor() for d in frames2], prec=prec)
+            with torch.cuda.stream(stream):
+                step(planm)
+                torch.cuda.synchronize()
+                nm = max(5, args.steps // 2)
+                evm = [[torch.cuda.Event(enable_timing=True) for _ in range(5)]
+                       for _ in range(nm)]
+                t0 = time.perf_counter()
+                for sidx in range(nm):
+                    step(planm, evm[sidx])
+                torch.cuda.synchronize()
+                vm = B * nm / (time.perf_counter() - t0)
+            sm = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evm]))
+                  for i, n in enumerate(stage_names)}
+            am = B * cov_flops(M, T) / (sm["covariance"] * 1e-3) / 1e12
+            mixed[pname] = {"frames_per_s": round(vm, 2),
+                            "stage_ms_per_step": {k: round(v, 4) for k, v in sm.items()},
+                            "covariance_tflops": round(am, 1),
+                            "covariance_frac_of_16bit_peak": round(am / PEAK_F16_MFMA_TFLOPS, 4)}
+            log(f"mixed {pname}: {vm:.1f} frames/s, stages {sm}")
+            del planm
+        out["mixed_precision"] = mixed
+        out["mixed_precision_note"] = ("covariance operands in FP16/BF16 with FP32 "
+                                       "accumulation; sketch and spectrum FP32; small dense "
+                                       "steps and peak-region denominators FP64")
+
         # ---- Method 1 on the same frames -----------------------------------
         del plan2
         frames1 = make_frames(fm.FM_METHOD_SAMPLE)

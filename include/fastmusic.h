@@ -61,10 +61,15 @@ typedef enum {
   FM_E_UNSUPPORTED = 4   /* valid but not supported by this build */
 } fm_status;
 
-/* Operand precision of the large contractions (covariance, sketch products,
- * steering projection).  Accumulation is FP32 in every mode; the small dense
- * steps (orthonormalisation, eigen-solves, peak-region denominators) are FP64
- * in every mode. */
+/* Operand precision of the covariance contraction (fm_covariance and the
+ * covariance stage of a plan).  Accumulation is FP32 in every mode.  In this
+ * build the sketch products and the steering projection run on the FP32
+ * matrix cores whatever the plan's precision (fm_subspace_project and
+ * fm_pseudospectrum reject 16-bit precisions with FM_E_UNSUPPORTED): a plain
+ * 16-bit rounding of R or of the steering vectors perturbs the peak-region
+ * denominators by more than 1e-2 dB.  The small dense steps
+ * (orthonormalisation, eigen-solves, peak-region denominators) are FP64 in
+ * every mode. */
 typedef enum {
   FM_FP32 = 0,   /* FP32 operands on FP32 MFMA */
   FM_BF16 = 1,   /* BF16 operands on BF16 MFMA */
@@ -224,7 +229,8 @@ typedef struct {
 /* Build a plan for n_frames frames (host array, copied): validates every
  * frame, builds the per-stage work lists (longest-first), uploads them and
  * allocates the plan's workspace.  Synchronises the device once.  Each
- * frame is computed exactly as the single-frame entry points compute it. */
+ * frame is computed exactly as the single-frame entry points compute it
+ * (with fm_covariance at the plan's precision `prec`). */
 fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,
                          fm_plan **out);
 fm_status fm_plan_destroy(fm_plan *plan);

@@ -280,7 +280,6 @@ FM_API fm_status fm_covariance(fm_ctx *ctx, void *stream, const void *X, int M, 
   fm_status st = check_cov(ctx, X, M, T, ldx, R, ldr);
   if (st != FM_OK) return st;
   if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "covariance: bad precision %d", (int)prec);
-  if (prec != FM_FP32) return fail(ctx, FM_E_UNSUPPORTED, "covariance: only FM_FP32 in this build");
   if ((st = set_dev(ctx)) != FM_OK) return st;
   FrameDev f = blank_frame();
   f.X = static_cast<const float2 *>(X);
@@ -405,12 +404,12 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kCov: return fm::launch_covariance(cls, fr, it, L.count, p->prec, s);
     case kOmega: return fm::launch_omega(cls, fr, it, L.count, 0, s);
     case kGather: return fm::launch_gather(cls, fr, it, L.count, s);
-    case kSketch: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, p->prec, s);
+    case kSketch: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, FM_FP32, s);
     case kGram: return fm::launch_gram(cls, fr, it, L.count, L.mode, s);
     case kSmall: return fm::launch_small(cls, fr, it, L.count, L.mode, s);
     case kApply: return fm::launch_apply(cls, fr, it, L.count, L.mode, s);
     case kSpecPrep: return fm::launch_spec_prep(fr, it, L.count, s);
-    case kSpec: return fm::launch_spectrum(cls, fr, it, L.count, L.n_class, p->prec, s);
+    case kSpec: return fm::launch_spectrum(cls, fr, it, L.count, L.n_class, FM_FP32, s);
     case kRefine: return fm::launch_refine(cls, fr, it, L.count, s);
     case kPeaks: return fm::launch_peaks(cls, fr, it, L.count, s);
   }
@@ -433,7 +432,6 @@ FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frame
   *out = nullptr;
   if (!frames || n_frames < 1) return fail(ctx, FM_E_ARG, "plan: need at least one frame");
   if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "plan: bad precision %d", (int)prec);
-  if (prec != FM_FP32) return fail(ctx, FM_E_UNSUPPORTED, "plan: only FM_FP32 in this build");
   for (int i = 0; i < n_frames; ++i) {
     const fm_frame &a = frames[i];
     fm_status st = check_cov(ctx, a.X, a.M, a.T, a.ldx, a.R, a.ldr);

@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void cov_fp32_kernel(FrameDev single,
 
 hipError_t launch_covariance(const FrameDev &single, const FrameDev *frames, const Item *items,
                              int n_items, fm_prec prec, hipStream_t s) {
-  (void)prec;
+  if (prec != FM_FP32) return launch_covariance16(single, frames, items, n_items, prec, s);
   if (items) {
     if (n_items <= 0) return hipSuccess;
     hipLaunchKernelGGL(cov_fp32_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames,

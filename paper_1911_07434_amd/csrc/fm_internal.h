@@ -86,6 +86,9 @@ enum ApplyMode { kApplyV = 0, kApplyUs = 1 };
 // ---------------------------------------------------------------------------
 hipError_t launch_covariance(const FrameDev &single, const FrameDev *frames,
                              const Item *items, int n_items, fm_prec prec, hipStream_t s);
+// 16-bit operand covariance (FM_FP16 / FM_BF16), FP32 accumulation
+hipError_t launch_covariance16(const FrameDev &single, const FrameDev *frames,
+                               const Item *items, int n_items, fm_prec prec, hipStream_t s);
 hipError_t launch_omega(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, int to_y, hipStream_t s);
 // nb = ceil(2n / 32): MFMA column blocks of the sketch (one launch per class)

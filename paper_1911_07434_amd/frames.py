@@ -85,13 +85,14 @@ class DeviceFrame:
 
 
 def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
-    """All four stages of one frame through the single-frame entry points."""
+    """All four stages of one frame through the single-frame entry points
+    (`prec` is the covariance operand precision; the other stages are FP32)."""
     s = fr.spec
     ctx.fm_covariance(fr.X, fr.R, prec, stream)
     if s.method == FM_METHOD_PROJECT:
         ctx.fm_subspace_project(fr.R, fr.Omega, s.q, s.K, fr.Us, fr.sigma, fr.status, s.rcond,
-                                prec, stream)
+                                0, stream)
     else:
         ctx.fm_subspace_sample(fr.R, fr.idx, s.K, fr.Us, fr.sigma, fr.status, s.rcond, stream)
-    ctx.fm_pseudospectrum(fr.Us, s.theta0_deg, s.dtheta_deg, s.L, fr.P, prec, stream)
+    ctx.fm_pseudospectrum(fr.Us, s.theta0_deg, s.dtheta_deg, s.L, fr.P, 0, stream)
     ctx.fm_peaks(fr.P, s.K, fr.peak_idx, fr.peak_val, fr.n_found, stream)

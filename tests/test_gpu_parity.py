@@ -389,12 +389,105 @@ def test_argument_validation(ctx):
     with pytest.raises(fm.FmError) as e:
         ctx.fm_pseudospectrum(Us, 0.0, -1.0, 10, P)             # dtheta <= 0
     assert e.value.status == fm.FM_E_ARG
-    X = torch.zeros((4, 8), dtype=torch.complex64, device="cuda")
     with pytest.raises(fm.FmError) as e:
-        ctx.fm_covariance(X, R, prec=fm.FM_BF16)                # not in this build
-    assert e.value.status in (fm.FM_E_UNSUPPORTED, fm.FM_OK)
+        ctx.fm_subspace_project(R, Om, 2, 3, Us, sig, st, prec=fm.FM_BF16)  # FP32 only
+    assert e.value.status == fm.FM_E_UNSUPPORTED
     small = fm.Context(0, 1024)
     with pytest.raises(fm.FmError) as e:
         small.fm_subspace_project(R, Om, 2, 3, Us, sig, st)     # arena too small
     assert e.value.status == fm.FM_E_WORKSPACE
     small.close()
+
+
+# ----------------------------------------------------------------------------
+# 16-bit covariance operands (FP32 accumulation)
+# ----------------------------------------------------------------------------
+
+DB_MIXED = 1e-2
+PRECS = {"fp16": fm.FM_FP16, "bf16": fm.FM_BF16}
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("M,T", [(8, 64), (200, 512), (257, 2048)])
+def test_covariance16_integer_bitwise(ctx, prec, M, T):
+    # |re|, |im| <= 8 are exact in FP16 and BF16; every partial sum is an
+    # exact integer in FP32, so the result is the oracle's bit for bit
+    say(f"cov16 int {prec} M={M} T={T}")
+    X = fmsynth.make_integer_frame(M, T, seed=3 * M + T)
+    R = torch.empty((M, M), dtype=torch.complex64, device="cuda")
+    ctx.fm_covariance(dev(X), R, prec=PRECS[prec])
+    torch.cuda.synchronize()
+    assert np.array_equal(R.cpu().numpy().astype(np.complex128), oracle.covariance(X))
+
+
+# bound: rounding each snapshot to 16 bits perturbs every product x_i conj(x_j)
+# by at most 2u relative (u = 2^-11 for FP16, 2^-8 for BF16); with many
+# snapshots the errors average down, with T = 3 they do not
+@pytest.mark.parametrize("prec,tol", [("fp16", 2 * 2.0 ** -11), ("bf16", 2 * 2.0 ** -8)])
+@pytest.mark.parametrize("M,T", [(64, 128), (300, 777), (130, 3), (1024, 2048)])
+def test_covariance16_gaussian(ctx, prec, tol, M, T):
+    say(f"cov16 gauss {prec} M={M} T={T}")
+    fr = fmsynth.make_frame(M, T, 3, 0.0, seed=M + 5 * T)
+    R = torch.empty((M, M), dtype=torch.complex64, device="cuda")
+    ctx.fm_covariance(dev(fr.X), R, prec=PRECS[prec])
+    torch.cuda.synchronize()
+    Rg = R.cpu().numpy()
+    Ro = oracle.covariance(fr.X, threads=oracle.default_threads())
+    assert np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro) <= tol
+    assert np.array_equal(Rg, Rg.conj().T)
+    assert np.all(np.diag(Rg).imag == 0)
+
+
+def _plan_one(ctx, name, method, seed, prec):
+    cfg = fmsynth.CONFIGS[name]
+    fr, _ = fmsynth.config_frame(name, seed=seed)
+    th0, dth, L = fmsynth.grid(cfg["L"])
+    if method == "project":
+        rnd, n, m = fmsynth.make_omega(fr.M, cfg["l"], seed), cfg["l"], fm.FM_METHOD_PROJECT
+    else:
+        rnd, n, m = fmsynth.make_idx(fr.M, cfg["p"], seed), cfg["p"], fm.FM_METHOD_SAMPLE
+    spec = FrameSpec(M=fr.M, T=fr.T, K=fr.K, method=m, n=n, q=cfg["q"], L=L, theta0_deg=th0,
+                     dtheta_deg=dth)
+    d = DeviceFrame(spec, X=torch.from_numpy(fr.X), rnd=torch.from_numpy(rnd))
+    plan = fm.Plan(ctx, [d.descriptor()], prec=prec)
+    plan.run()
+    torch.cuda.synchronize()
+    plan.close()
+    kw = dict(Omega=rnd, q=cfg["q"]) if method == "project" else dict(idx=rnd)
+    ref = oracle.run_frame(fr.X, fr.K, method, th0, dth, L, threads=oracle.default_threads(), **kw)
+    return d.results(), ref
+
+
+@pytest.mark.parametrize("name,method,seed", [("c1", "project", 31), ("c2", "project", 32),
+                                              ("c2", "sample", 33)])
+def test_mixed_fp16_end_to_end(ctx, name, method, seed):
+    say(f"mixed fp16 {name} {method}")
+    got, ref = _plan_one(ctx, name, method, seed, fm.FM_FP16)
+    err = db_err(got["P"], ref["P"])
+    say(f"  max |dP| = {err:.3g} dB")
+    assert got["status"] == 0
+    assert err <= DB_MIXED
+    assert got["n_found"] == len(ref["peak_idx"])
+    for pk in ref["peak_idx"]:
+        assert np.min(np.abs(got["peak_idx"] - pk)) <= 1
+
+
+def test_mixed_plan_equals_single_calls_bitwise(ctx):
+    frames = _mixed_frames(5, seed=9)
+    for prec in (fm.FM_FP16, fm.FM_BF16):
+        alone = []
+        for spec, X, rnd in frames:
+            d = DeviceFrame(spec, X=torch.from_numpy(X), rnd=torch.from_numpy(rnd))
+            run_single(ctx, d, prec=prec)
+            torch.cuda.synchronize()
+            alone.append(d.results())
+        devs = [DeviceFrame(s, X=torch.from_numpy(X), rnd=torch.from_numpy(r))
+                for s, X, r in frames]
+        plan = fm.Plan(ctx, [d.descriptor() for d in devs], prec=prec)
+        plan.run()
+        torch.cuda.synchronize()
+        for a, d in zip(alone, devs):
+            b = d.results()
+            assert np.array_equal(a["R"], b["R"])
+            assert np.array_equal(a["P"], b["P"])
+        plan.close()
