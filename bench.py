@@ -64,6 +64,88 @@ def pmc_traffic(n_frames):
     return float(b.group(1)) * n_frames
 
 
+def serve_legs(ctx, fm, torch, seconds, seed):
+    """Serving workload: Poisson arrivals at 2000 frames/s, M uniform over
+    {128..4096} (powers of two), T ~ U[64, 4096], K ~ U[1, 32], SNR ~
+    U[-10, 30] dB, l = min(K+8, 40), q = 2, 18001-angle grid; continuous
+    batching on two streams with HBM-budget admission.  Standard MUSIC
+    (rocSOLVER eigen-decomposition per frame) is run on the head of the same
+    arrival trace."""
+    from paper_1911_07434_amd.serve import GpuExecutor, Server, WallClock, poisson_arrivals
+    free, _total = torch.cuda.mem_get_info()
+    budget = int(min(200 << 30, free - (24 << 30)))
+    res = {"arrival_rate_hz": 2000.0, "trace_seconds": seconds, "hbm_budget_bytes": budget,
+           "streams": 2}
+    for pname, prec in (("fp32", fm.FM_FP32), ("fp16", fm.FM_FP16)):
+        reqs = poisson_arrivals(2000.0, seconds, seed=seed + 1)
+        ex = GpuExecutor(ctx, pool_bytes=budget, n_streams=2, prec=prec)
+        clock = WallClock()
+        ex.start(clock)
+        st = Server(ex, budget_bytes=budget, n_streams=2, max_batch=64, clock=clock).run(reqs)
+        torch.cuda.synchronize()
+        res[pname] = st.summary()
+        log(f"serving {pname}: {res[pname]}")
+        del ex
+        torch.cuda.empty_cache()
+    # standard MUSIC under the same arrivals (head of the trace)
+    reqs = poisson_arrivals(2000.0, seconds, seed=seed + 1, max_frames=120)
+    ex = PlainMusicExecutor(ctx, pool_bytes=min(budget, 64 << 30), n_streams=2)
+    clock = WallClock()
+    ex.start(clock)
+    st = Server(ex, budget_bytes=min(budget, 64 << 30), n_streams=2, max_batch=64,
+                clock=clock).run(reqs)
+    torch.cuda.synchronize()
+    res["plain_music_head_of_trace"] = st.summary()
+    log(f"serving plain MUSIC: {res['plain_music_head_of_trace']}")
+    del ex
+    torch.cuda.empty_cache()
+    return res
+
+
+def _plain_music_executor():
+    from paper_1911_07434_amd.serve import GpuExecutor
+
+    class PlainMusic(GpuExecutor):
+        """Standard MUSIC per frame: the library's covariance, rocSOLVER's
+        eigen-decomposition (torch.linalg.eigh), the library's spectrum and
+        peaks -- the comparator, not part of the library."""
+
+        def plan_bytes(self, reqs):
+            return 256
+
+        def launch(self, reqs, stream_idx, plan_mem):
+            torch = self.torch
+            s = self.streams[stream_idx]
+            with torch.cuda.stream(s):
+                for r in reqs:
+                    d = self._descriptor(r)
+                    lay, _ = self._layout(r)
+                    o = r.mem[0]
+                    R = self.pool[o + lay["R"]:o + lay["R"] + r.M * r.M * 8].view(
+                        torch.complex64).view(r.M, r.M)
+                    self.ctx.fm_covariance(self.X[r.M][:, :r.T], R, stream=s)
+                    _w, V = torch.linalg.eigh(R)
+                    Us = V[:, r.M - r.K:].flip(-1).transpose(0, 1).to(torch.complex128).contiguous()
+                    P = self.pool[o + lay["P"]:o + lay["P"] + r.L * 4].view(torch.float32)
+                    pi = self.pool[o + lay["pidx"]:o + lay["pidx"] + r.K * 4].view(torch.int32)
+                    pv = self.pool[o + lay["pval"]:o + lay["pval"] + r.K * 4].view(torch.float32)
+                    nf = self.pool[o + lay["nf"]:o + lay["nf"] + 4].view(torch.int32)
+                    self.ctx.fm_pseudospectrum(Us, d.theta0_deg, d.dtheta_deg, r.L, P, stream=s)
+                    self.ctx.fm_peaks(P, r.K, pi, pv, nf, stream=s)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(s)
+            return (None, ev)
+
+        def release(self, handle):
+            pass
+
+    return PlainMusic
+
+
+def PlainMusicExecutor(*a, **k):
+    return _plain_music_executor()(*a, **k)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +156,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="time only the main step (for profiler runs)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the Poisson arrival trace of the serving leg (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -283,6 +367,12 @@ def main():
         }
         out["frame_latency_ms_alone"] = {"p50": round(float(np.percentile(lat, 50)), 3),
                                          "p99": round(float(np.percentile(lat, 99)), 3)}
+
+    # ---- serving: Poisson arrivals of mixed-shape frames ---------------------
+    if not args.no_extra and args.serve_seconds > 0:
+        del frames2
+        torch.cuda.empty_cache()
+        out["serving"] = serve_legs(ctx, fm, torch, args.serve_seconds, args.seed)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample -----------------
     if not args.no_cpu:

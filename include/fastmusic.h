@@ -233,6 +233,23 @@ typedef struct {
  * (with fm_covariance at the plan's precision `prec`). */
 fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,
                          fm_plan **out);
+/* Device bytes a plan for these frames needs (workspace, descriptors and
+ * work lists); 0 if a frame is invalid.  Pure host computation. */
+size_t fm_plan_bytes(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec);
+
+/* As fm_plan_create, but for callers that cannot allocate or synchronise
+ * (a serving loop with its own device memory pool): the plan lives in the
+ * caller's block dev_mem[0, dev_bytes) (>= fm_plan_bytes, 256-byte aligned),
+ * its descriptors and work lists are uploaded with asynchronous copies on
+ * `stream`, and nothing is allocated on the device or synchronised.  Run it
+ * on the same stream (or after it).  The block must stay valid until the
+ * plan's work has completed; fm_plan_destroy on such a plan neither
+ * synchronises nor frees device memory. */
+fm_status fm_plan_create_in(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,
+                            void *dev_mem, size_t dev_bytes, void *stream, fm_plan **out);
+
+/* Destroy a plan.  A plan from fm_plan_create first waits for the device to
+ * go idle and frees its memory. */
 fm_status fm_plan_destroy(fm_plan *plan);
 
 /* Device bytes the plan allocated for its workspace and work lists. */

@@ -29,7 +29,7 @@ EXPORTS = (
     "fm_covariance", "fm_subspace_sample", "fm_subspace_project", "fm_pseudospectrum",
     "fm_peaks", "fm_plan_create", "fm_plan_destroy", "fm_plan_workspace_bytes",
     "fm_plan_covariance", "fm_plan_subspace", "fm_plan_pseudospectrum", "fm_plan_peaks",
-    "fm_plan_run",
+    "fm_plan_run", "fm_plan_bytes", "fm_plan_create_in",
 )
 
 
@@ -87,6 +87,8 @@ def load_library(path: str = LIB_PATH):
         "fm_plan_pseudospectrum": ([P, P], I),
         "fm_plan_peaks": ([P, P], I),
         "fm_plan_run": ([P, P, I], I),
+        "fm_plan_bytes": ([P, C.POINTER(fm_frame), I, I], Z),
+        "fm_plan_create_in": ([P, C.POINTER(fm_frame), I, I, P, Z, P, C.POINTER(P)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -166,15 +168,29 @@ class Context:
                                      _ptr(idx), _ptr(val), _ptr(n_found)))
 
 
-class Plan:
-    """A batch of frames (fm_frame list) run through one launch per stage."""
+def plan_bytes(ctx: Context, frames: list[fm_frame], prec=FM_FP32) -> int:
+    arr = (fm_frame * len(frames))(*frames)
+    return int(ctx.lib.fm_plan_bytes(ctx.h, arr, len(frames), prec))
 
-    def __init__(self, ctx: Context, frames: list[fm_frame], prec=FM_FP32):
+
+class Plan:
+    """A batch of frames (fm_frame list) run through one launch per stage.
+
+    With dev_mem (a device pointer) and dev_bytes the plan lives in that
+    caller-owned block and is uploaded asynchronously on `stream`
+    (fm_plan_create_in); otherwise it allocates (fm_plan_create)."""
+
+    def __init__(self, ctx: Context, frames: list[fm_frame], prec=FM_FP32, dev_mem=None,
+                 dev_bytes=0, stream=None):
         self.ctx = ctx
         self.frames = (fm_frame * len(frames))(*frames)
         self.h = C.c_void_p()
-        ctx.check(ctx.lib.fm_plan_create(ctx.h, self.frames, len(frames), prec,
-                                         C.byref(self.h)))
+        if dev_mem is None:
+            ctx.check(ctx.lib.fm_plan_create(ctx.h, self.frames, len(frames), prec,
+                                             C.byref(self.h)))
+        else:
+            ctx.check(ctx.lib.fm_plan_create_in(ctx.h, self.frames, len(frames), prec, dev_mem,
+                                                dev_bytes, _stream(stream), C.byref(self.h)))
 
     def close(self):
         if self.h:

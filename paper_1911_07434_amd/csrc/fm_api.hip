@@ -33,6 +33,8 @@ struct fm_plan {
   size_t ws_bytes = 0;
   Item *items_d = nullptr;
   size_t items_bytes = 0;
+  std::vector<Item> items_h;  // host copy (source of the asynchronous upload)
+  bool owned = true;          // device memory allocated by the plan itself
   // a launch = (kind, mode/class, offset into items_d, count)
   struct Launch {
     int kind, mode, n_class;
@@ -426,10 +428,15 @@ fm_status run_list(fm_plan *p, const std::vector<fm_plan::Launch> &v, void *stre
 
 }  // namespace
 
-FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,
-                                fm_plan **out) {
-  if (!ctx || !out) return FM_E_ARG;
-  *out = nullptr;
+// Builds a plan.  dev == nullptr: the plan allocates its device memory and
+// uploads synchronously.  Otherwise everything lives in the caller's block
+// [dev, dev + dev_bytes) and the upload is enqueued on `stream`; with
+// dry_run only *need is computed.
+static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,
+                            char *dev, size_t dev_bytes, hipStream_t stream, bool dry_run,
+                            size_t *need, fm_plan **out) {
+  if (!ctx || (!out && !dry_run)) return FM_E_ARG;
+  if (out) *out = nullptr;
   if (!frames || n_frames < 1) return fail(ctx, FM_E_ARG, "plan: need at least one frame");
   if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "plan: bad precision %d", (int)prec);
   for (int i = 0; i < n_frames; ++i) {
@@ -446,13 +453,14 @@ FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frame
       return fail(ctx, st, "plan frame %d: %s", i, m.c_str());
     }
   }
-  fm_status st = set_dev(ctx);
+  fm_status st = dry_run ? FM_OK : set_dev(ctx);
   if (st != FM_OK) return st;
   fm_plan *p = new (std::nothrow) fm_plan;
   if (!p) return fail(ctx, FM_E_WORKSPACE, "plan: out of host memory");
   p->ctx = ctx;
   p->prec = prec;
   p->n_frames = n_frames;
+  p->owned = dev == nullptr;
 
   // workspace: frames packed back to back
   std::vector<WsLayout> lay(n_frames);
@@ -464,10 +472,17 @@ FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frame
     total += lay[i].total;
   }
   p->ws_bytes = total;
-  hipError_t e = hipMalloc((void **)&p->ws, std::max<size_t>(total, 256));
-  if (e != hipSuccess) {
-    delete p;
-    return hip_fail(ctx, e, "plan workspace hipMalloc");
+  hipError_t e = hipSuccess;
+  if (dry_run) {
+    p->ws = nullptr;
+  } else if (p->owned) {
+    e = hipMalloc((void **)&p->ws, std::max<size_t>(total, 256));
+    if (e != hipSuccess) {
+      delete p;
+      return hip_fail(ctx, e, "plan workspace hipMalloc");
+    }
+  } else {
+    p->ws = dev;  // descriptors and work lists follow the workspace
   }
   p->frames_h.resize(n_frames);
   for (int i = 0; i < n_frames; ++i) {
@@ -516,11 +531,42 @@ FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frame
   });
   auto rows = [](int M, int r) { return (M + r - 1) / r; };
 
+  // Covariance tiles, XCD-aware: workgroup w of a launch is dispatched to XCD
+  // w mod 8, each XCD with its own L2.  Frames are dealt to the 8 XCDs
+  // (largest first onto the least loaded) and position w of the list takes
+  // the next tile of XCD (w mod 8)'s frames, so all tiles of a frame share
+  // one L2 and each window of its snapshots is fetched once per XCD.
   size_t b0 = begin();
-  for (int i : order) {
-    const int nt = (frames[i].M + fm::kCovTile - 1) / fm::kCovTile;
-    for (int ti = 0; ti < nt; ++ti)
-      for (int tj = 0; tj <= ti; ++tj) items.push_back({i, ti, tj, 0});
+  {
+    constexpr int kXcd = 8;
+    std::vector<std::vector<Item>> q(kXcd);
+    std::vector<double> load(kXcd, 0.0);
+    for (int i : order) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      const int nt = (frames[i].M + fm::kCovTile - 1) / fm::kCovTile;
+      load[x] += (double)nt * (nt + 1) / 2 * frames[i].T;
+      for (int ti = 0; ti < nt; ++ti)
+        for (int tj = 0; tj <= ti; ++tj) q[x].push_back({i, ti, tj, 0});
+    }
+    std::vector<size_t> pos(kXcd, 0);
+    size_t left = 0;
+    for (auto &v : q) left += v.size();
+    while (left > 0) {
+      for (int x = 0; x < kXcd && left > 0; ++x) {
+        int y = x;
+        if (pos[y] >= q[y].size()) {  // this XCD's frames are done: take from the fullest
+          size_t best = 0;
+          for (int z = 0; z < kXcd; ++z)
+            if (q[z].size() - pos[z] > best) { best = q[z].size() - pos[z]; y = z; }
+          // steal from the back so y's next items keep their positions
+          items.push_back(q[y].back());
+          q[y].pop_back();
+        } else {
+          items.push_back(q[y][pos[y]++]);
+        }
+        --left;
+      }
+    }
   }
   add(p->cov, kCov, 0, 0, b0);
 
@@ -611,13 +657,37 @@ FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frame
   add(p->peaks, kPeaks, 0, 0, b0);
 
   p->items_bytes = items.size() * sizeof(Item);
-  e = hipMalloc((void **)&p->items_d, std::max<size_t>(p->items_bytes, 256));
-  if (e == hipSuccess) e = hipMalloc((void **)&p->frames_d, sizeof(FrameDev) * n_frames);
-  if (e == hipSuccess)
-    e = hipMemcpy(p->items_d, items.data(), p->items_bytes, hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(p->frames_d, p->frames_h.data(), sizeof(FrameDev) * n_frames,
-                  hipMemcpyHostToDevice);
+  const size_t frames_bytes = align256(sizeof(FrameDev) * n_frames);
+  const size_t total_dev = total + frames_bytes + align256(std::max<size_t>(p->items_bytes, 16));
+  if (need) *need = total_dev;
+  if (dry_run) {
+    delete p;
+    return FM_OK;
+  }
+  p->items_h = std::move(items);
+  if (p->owned) {
+    e = hipMalloc((void **)&p->items_d, std::max<size_t>(p->items_bytes, 256));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->frames_d, sizeof(FrameDev) * n_frames);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->items_d, p->items_h.data(), p->items_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->frames_d, p->frames_h.data(), sizeof(FrameDev) * n_frames,
+                    hipMemcpyHostToDevice);
+  } else {
+    if (total_dev > dev_bytes) {
+      p->ws = nullptr;
+      delete p;
+      return fail(ctx, FM_E_WORKSPACE, "plan: needs %zu device bytes, given %zu", total_dev,
+                  dev_bytes);
+    }
+    p->frames_d = reinterpret_cast<FrameDev *>(dev + total);
+    p->items_d = reinterpret_cast<Item *>(dev + total + frames_bytes);
+    e = hipMemcpyAsync(p->items_d, p->items_h.data(), p->items_bytes, hipMemcpyHostToDevice,
+                       stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->frames_d, p->frames_h.data(), sizeof(FrameDev) * n_frames,
+                         hipMemcpyHostToDevice, stream);
+  }
   if (e != hipSuccess) {
     fm_plan_destroy(p);
     return hip_fail(ctx, e, "plan upload");
@@ -626,16 +696,38 @@ FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frame
   return FM_OK;
 }
 
+FM_API fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,
+                                fm_plan **out) {
+  return plan_build(ctx, frames, n_frames, prec, nullptr, 0, nullptr, false, nullptr, out);
+}
+
+FM_API size_t fm_plan_bytes(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec) {
+  size_t need = 0;
+  if (plan_build(ctx, frames, n_frames, prec, nullptr, 0, nullptr, true, &need, nullptr) != FM_OK)
+    return 0;
+  return need;
+}
+
+FM_API fm_status fm_plan_create_in(fm_ctx *ctx, const fm_frame *frames, int n_frames,
+                                   fm_prec prec, void *dev_mem, size_t dev_bytes, void *stream,
+                                   fm_plan **out) {
+  if (!dev_mem) return fail(ctx, FM_E_ARG, "plan_create_in: null device memory");
+  return plan_build(ctx, frames, n_frames, prec, static_cast<char *>(dev_mem), dev_bytes,
+                    (hipStream_t)stream, false, nullptr, out);
+}
+
 FM_API fm_status fm_plan_destroy(fm_plan *p) {
   if (!p) return FM_E_ARG;
   hipSetDevice(p->ctx->device);
-  hipDeviceSynchronize();
+  if (p->owned) hipDeviceSynchronize();
   if (p->gexec) hipGraphExecDestroy(p->gexec);
   if (p->graph) hipGraphDestroy(p->graph);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
-  if (p->items_d) hipFree(p->items_d);
-  if (p->frames_d) hipFree(p->frames_d);
-  if (p->ws) hipFree(p->ws);
+  if (p->owned) {
+    if (p->items_d) hipFree(p->items_d);
+    if (p->frames_d) hipFree(p->frames_d);
+    if (p->ws) hipFree(p->ws);
+  }
   delete p;
   return FM_OK;
 }
