@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="time only the main step (for profiler runs)")
+    ap.add_argument("--prec", choices=("fp32", "fp16", "bf16"), default="fp32",
+                    help="covariance operand precision of the main timed step")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the Poisson arrival trace of the serving leg (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -209,7 +211,8 @@ def main():
         return out
 
     frames2 = make_frames(fm.FM_METHOD_PROJECT)
-    plan2 = fm.Plan(ctx, [d.descriptor() for d in frames2])
+    main_prec = {"fp32": fm.FM_FP32, "fp16": fm.FM_FP16, "bf16": fm.FM_BF16}[args.prec]
+    plan2 = fm.Plan(ctx, [d.descriptor() for d in frames2], prec=main_prec)
     log(f"plan workspace {plan2.workspace_bytes() / 2**20:.0f} MiB")
 
     stage_names = ("covariance", "subspace", "pseudospectrum", "peaks")
@@ -251,10 +254,12 @@ def main():
 
     cov_ms = stage_ms["covariance"]
     achieved = B * cov_flops(M, T) / (cov_ms * 1e-3) / 1e12
-    traffic = pmc_traffic(B)
-    roofline = {"bound": "mfma", "kernel": "cov_fp32_kernel", "achieved": round(achieved, 2),
-                "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+    traffic = pmc_traffic(B) if args.prec == "fp32" else None
+    peak = PEAK_FP32_MFMA_TFLOPS if args.prec == "fp32" else PEAK_F16_MFMA_TFLOPS
+    kname = "cov_fp32_kernel" if args.prec == "fp32" else "cov16_kernel"
+    roofline = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 2),
+                "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4),
                 "traffic": traffic,
                 "launch_ms": round(cov_ms, 4),
                 "algorithmic_flops_per_launch": B * cov_flops(M, T)}
@@ -262,7 +267,8 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "frames/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.prec if args.prec == "fp32" else args.prec + "+fp32+fp64",
         "data": "synthetic",
         "config": {"workload": f"fast-MUSIC Method 2, M={M} T={T} K={K} l={L_SKETCH} q={Q_ITERS} "
                                f"L={L_GRID} SNR={SNR_DB:g}dB, {B} frames per step",

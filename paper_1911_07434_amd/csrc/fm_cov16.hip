@@ -52,20 +52,27 @@ __device__ inline void tile_of(int b, int &ti, int &tj) {
 }
 
 // Global -> registers for one stage: 128 rows x 32 complex snapshots of one
-// operand = 2048 float4 (two snapshots each); 8 per thread.
+// operand = 2048 float4 (two snapshots each); 8 per thread.  Full stages take
+// the unconditional path; only the last, ragged stage checks T.
 __device__ __forceinline__ void stage_load(float4 (&v)[8], const FrameDev &f, int row0, int t0) {
   const int M = f.M, T = f.T;
+  const int tsub = 2 * (threadIdx.x & 15);
+  if (t0 + kBK <= T) {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int e = threadIdx.x + 256 * j;   // 0..2047
-    const int row = min(row0 + (e >> 4), M - 1);
-    const int tp = t0 + 2 * (e & 15);      // first snapshot of the pair
-    const float2 *p = f.X + (size_t)row * f.ldx + tp;
-    if (tp + 1 < T) {
-      v[j] = *(const gfloat4 *)p;
-    } else {
+    for (int j = 0; j < 8; ++j) {
+      const int row = min(row0 + ((threadIdx.x >> 4) + 16 * j), M - 1);
+      v[j] = *(const gfloat4 *)(f.X + (size_t)row * f.ldx + t0 + tsub);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int row = min(row0 + ((threadIdx.x >> 4) + 16 * j), M - 1);
+      const int tp = t0 + tsub;
+      const float2 *p = f.X + (size_t)row * f.ldx + tp;
       v[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (tp < T) {
+      if (tp + 1 < T) {
+        v[j] = *(const gfloat4 *)p;
+      } else if (tp < T) {
         const float2 x = *(FM_GLOBAL const float2 *)p;
         v[j].x = x.x;
         v[j].y = x.y;
@@ -74,16 +81,19 @@ __device__ __forceinline__ void stage_load(float4 (&v)[8], const FrameDev &f, in
   }
 }
 
+// registers -> LDS, converted to 16 bits (one 8-byte store per float4)
 template <class H>
-__device__ __forceinline__ void stage_store(const float4 (&v)[8], H *lds) {
+__device__ __forceinline__ void stage_store(const float4 (&v)[8], H *lds, int base) {
+  typedef H h4 __attribute__((ext_vector_type(4)));
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int e = threadIdx.x + 256 * j;
-    H *d = lds + (e >> 4) * kRowHalves + 4 * (e & 15);
-    d[0] = (H)v[j].x;
-    d[1] = (H)v[j].y;
-    d[2] = (H)v[j].z;
-    d[3] = (H)v[j].w;
+    const int row = (threadIdx.x >> 4) + 16 * j;
+    h4 w;
+    w[0] = (H)v[j].x;
+    w[1] = (H)v[j].y;
+    w[2] = (H)v[j].z;
+    w[3] = (H)v[j].w;
+    *(h4 *)(lds + base + row * kRowHalves + 4 * (threadIdx.x & 15)) = w;
   }
 }
 
@@ -93,16 +103,16 @@ __device__ __forceinline__ void cov16_tile(const FrameDev &f, int ti, int tj, H 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wi = wave >> 1, wj = wave & 1;
-  const int M = f.M, T = f.T;
+  const int T = f.T;
   const int r = lane & 31, h = lane >> 5;
   const bool diag = ti == tj;
   // the upper 64x64 block of a diagonal tile mirrors the lower one: that wave
   // still loads and synchronises, but skips its MFMAs and stores
   const bool active = !(diag && wi < wj);
   const int ra = ti * kCovTile, rb = tj * kCovTile;
-  // LDS: [buffer][A|B][128 rows][kRowHalves]
-  H *bufA[2] = {lds, lds + 2 * kTileHalves};
-  H *bufB[2] = {diag ? bufA[0] : lds + kTileHalves, diag ? bufA[1] : lds + 3 * kTileHalves};
+  // LDS offsets (in halves): [buffer][A|B][128 rows][kRowHalves]; a diagonal
+  // tile reads B from A's buffer
+  const int offB = diag ? 0 : kTileHalves;
 
   floatx16 accR[2][2], accI[2][2];
 #pragma unroll
@@ -119,25 +129,26 @@ __device__ __forceinline__ void cov16_tile(const FrameDev &f, int ti, int tj, H 
   float4 va[8], vb[8];
   stage_load(va, f, ra, 0);
   if (!diag) stage_load(vb, f, rb, 0);
-  stage_store<H>(va, bufA[0]);
-  if (!diag) stage_store<H>(vb, bufB[0]);
+  stage_store<H>(va, lds, 0);
+  if (!diag) stage_store<H>(vb, lds, kTileHalves);
   __syncthreads();
+  const int rowA = (wi * 64 + r) * kRowHalves + 8 * h;
+  const int rowB = (wj * 64 + r) * kRowHalves + 8 * h;
   for (int st = 0; st < nst; ++st) {
     const bool more = st + 1 < nst;
     if (more) {
       stage_load(va, f, ra, (st + 1) * kBK);
       if (!diag) stage_load(vb, f, rb, (st + 1) * kBK);
     }
+    const int cur = (st & 1) * 2 * kTileHalves;
     if (active) {
-      const H *A = bufA[st & 1];
-      const H *B = bufB[st & 1];
 #pragma unroll
       for (int ks = 0; ks < kBK / 8; ++ks) {
         vec a[2], ap[2], b[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          a[q] = *(const vec *)(A + (wi * 64 + 32 * q + r) * kRowHalves + 16 * ks + 8 * h);
-          b[q] = *(const vec *)(B + (wj * 64 + 32 * q + r) * kRowHalves + 16 * ks + 8 * h);
+          a[q] = *(const vec *)(lds + cur + rowA + 32 * q * kRowHalves + 16 * ks);
+          b[q] = *(const vec *)(lds + cur + offB + rowB + 32 * q * kRowHalves + 16 * ks);
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             ap[q][2 * c] = a[q][2 * c + 1];
@@ -154,12 +165,14 @@ __device__ __forceinline__ void cov16_tile(const FrameDev &f, int ti, int tj, H 
       }
     }
     if (more) {
-      stage_store<H>(va, bufA[(st + 1) & 1]);
-      if (!diag) stage_store<H>(vb, bufB[(st + 1) & 1]);
+      const int nxt = ((st + 1) & 1) * 2 * kTileHalves;
+      stage_store<H>(va, lds, nxt);
+      if (!diag) stage_store<H>(vb, lds, nxt + kTileHalves);
     }
     __syncthreads();
   }
   if (!active) return;
+  const int M = f.M;
 
   const int ib = ra + wi * 64, jb = rb + wj * 64;
   const float Tf = (float)T;
