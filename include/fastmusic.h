@@ -61,15 +61,21 @@ typedef enum {
   FM_E_UNSUPPORTED = 4   /* valid but not supported by this build */
 } fm_status;
 
-/* Operand precision of the covariance contraction (fm_covariance and the
- * covariance stage of a plan).  Accumulation is FP32 in every mode.  In this
- * build the sketch products and the steering projection run on the FP32
- * matrix cores whatever the plan's precision (fm_subspace_project and
- * fm_pseudospectrum reject 16-bit precisions with FM_E_UNSUPPORTED): a plain
- * 16-bit rounding of R or of the steering vectors perturbs the peak-region
- * denominators by more than 1e-2 dB.  The small dense steps
- * (orthonormalisation, eigen-solves, peak-region denominators) are FP64 in
- * every mode. */
+/* Operand precision of the matrix-core products.  Accumulation is FP32 in
+ * every mode.
+ *   covariance (fm_covariance, stage 1 of a plan): operands rounded to the
+ *     given precision.
+ *   pseudo-spectrum (fm_pseudospectrum, stage 3 of a plan): FM_FP32 uses FP32
+ *     products; FM_FP16 splits U_s and the steering twiddles into FP16 hi + lo
+ *     halves and accumulates hi*hi + hi*lo + lo*hi (~22-bit products).
+ *     fm_pseudospectrum rejects FM_BF16 (FM_E_UNSUPPORTED); a plan at either
+ *     16-bit precision runs the FP16 split spectrum.
+ *   sketch products (fm_subspace_*, stage 2 of a plan): FP32 in every mode
+ *     (fm_subspace_project rejects 16-bit precisions with FM_E_UNSUPPORTED): a
+ *     plain 16-bit rounding of R perturbs the peak-region denominators by more
+ *     than 1e-2 dB.
+ * The small dense steps (orthonormalisation, eigen-solves, peak-region
+ * denominators) are FP64 in every mode. */
 typedef enum {
   FM_FP32 = 0,   /* FP32 operands on FP32 MFMA */
   FM_BF16 = 1,   /* BF16 operands on BF16 MFMA */
@@ -170,9 +176,10 @@ fm_status fm_subspace_project(fm_ctx *ctx, void *stream, const void *R, int M, i
 /* ------------------------------------------------------------------------ */
 
 /* P_l = 1 / (M - ||U_s^H a(theta_l)||^2) on the grid theta_l.  The bulk of
- * the grid is evaluated with FP32 (or compensated BF16/FP16) products; every
- * point whose denominator falls below M/16 -- the cancellation-prone region
- * around peaks -- is recomputed in FP64.  A denominator below M*2^-53 is
+ * the grid is evaluated with FP32 products (prec FM_FP32) or compensated
+ * FP16 hi + lo products (prec FM_FP16); every point whose denominator falls
+ * below M/16 -- the cancellation-prone region around peaks -- is recomputed
+ * in FP64.  A denominator below M*2^-53 is
  * clamped there (the pole of a noiseless on-grid source).
  *   Us  complex128 [K][M] orthonormal columns (stage 2 output)
  *   P   float32 [L] (linear scale)
@@ -229,8 +236,10 @@ typedef struct {
 /* Build a plan for n_frames frames (host array, copied): validates every
  * frame, builds the per-stage work lists (longest-first), uploads them and
  * allocates the plan's workspace.  Synchronises the device once.  Each
- * frame is computed exactly as the single-frame entry points compute it
- * (with fm_covariance at the plan's precision `prec`). */
+ * frame is computed exactly as the single-frame entry points compute it:
+ * fm_covariance at the plan's precision `prec`, fm_subspace_* at FM_FP32,
+ * fm_pseudospectrum at FM_FP32 for an FP32 plan and at FM_FP16 for a 16-bit
+ * plan. */
 fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,
                          fm_plan **out);
 /* Device bytes a plan for these frames needs (workspace, descriptors and

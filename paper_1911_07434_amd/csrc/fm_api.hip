@@ -51,7 +51,8 @@ struct fm_plan {
 
 namespace {
 
-enum Kind { kCov, kOmega, kGather, kSketch, kGram, kSmall, kApply, kSpecPrep, kSpec, kRefine,
+enum Kind { kCov, kOmega, kGather, kSketch, kGram, kSmall, kApply, kSpecPrep, kSpec, kSplit,
+             kSpec16, kRefine,
             kPeaks };
 
 fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
@@ -176,6 +177,7 @@ fm_status check_peaks(fm_ctx *c, const void *P, int L, int K, const void *idx, c
 
 // MFMA row/column block classes (one kernel instantiation per class)
 int spec_nb(int K) { return (2 * K + 15) / 16; }
+int spec16_nb(int K) { return (K + 7) / 8; }
 int sketch_nb(int n) { return (2 * n + 31) / 32; }
 
 // ---------------------------------------------------------------------------
@@ -350,7 +352,8 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
   fm_status st = check_spec(ctx, Us, M, K, theta0_deg, dtheta_deg, L, P);
   if (st != FM_OK) return st;
   if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "pseudospectrum: bad precision %d", (int)prec);
-  if (prec != FM_FP32) return fail(ctx, FM_E_UNSUPPORTED, "pseudospectrum: only FM_FP32 in this build");
+  if (prec == FM_BF16)
+    return fail(ctx, FM_E_UNSUPPORTED, "pseudospectrum: FM_FP32 or FM_FP16 (compensated) only");
   const size_t uf_bytes = align256((size_t)M * K * 8);
   const size_t need = uf_bytes + align256((size_t)(L + 1) * 4);
   if (need > ctx->arena_bytes)
@@ -367,8 +370,13 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
   f.dtheta = dtheta_deg;
   f.P = P;
   hipStream_t s = (hipStream_t)stream;
-  FM_CHECK_LAUNCH(ctx, fm::launch_uf(f, s));
-  FM_CHECK_LAUNCH(ctx, fm::launch_spectrum(f, nullptr, nullptr, 0, spec_nb(K), prec, s));
+  if (prec == FM_FP32) {
+    FM_CHECK_LAUNCH(ctx, fm::launch_uf(f, s));
+    FM_CHECK_LAUNCH(ctx, fm::launch_spectrum(f, nullptr, nullptr, 0, spec_nb(K), prec, s));
+  } else {
+    FM_CHECK_LAUNCH(ctx, fm::launch_split(f, nullptr, nullptr, 0, s));
+    FM_CHECK_LAUNCH(ctx, fm::launch_spectrum16(f, nullptr, nullptr, 0, spec16_nb(K), s));
+  }
   FM_CHECK_LAUNCH(ctx, fm::launch_refine(f, nullptr, nullptr, 0, s));
   return FM_OK;
 }
@@ -412,6 +420,8 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kApply: return fm::launch_apply(cls, fr, it, L.count, L.mode, s);
     case kSpecPrep: return fm::launch_spec_prep(fr, it, L.count, s);
     case kSpec: return fm::launch_spectrum(cls, fr, it, L.count, L.n_class, FM_FP32, s);
+    case kSplit: return fm::launch_split(cls, fr, it, L.count, s);
+    case kSpec16: return fm::launch_spectrum16(cls, fr, it, L.count, L.n_class, s);
     case kRefine: return fm::launch_refine(cls, fr, it, L.count, s);
     case kPeaks: return fm::launch_peaks(cls, fr, it, L.count, s);
   }
@@ -638,15 +648,30 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
   add(p->sub, kApply, fm::kApplyUs, 0, b0);
 
-  b0 = begin();
-  for (int i : order) items.push_back({i, 0, 0, 0});
-  add(p->spec, kSpecPrep, 0, 0, b0);
-  for (int nb = 1; nb <= 8; ++nb) {
+  if (prec == FM_FP32) {
+    b0 = begin();
+    for (int i : order) items.push_back({i, 0, 0, 0});
+    add(p->spec, kSpecPrep, 0, 0, b0);
+    for (int nb = 1; nb <= 8; ++nb) {
+      b0 = begin();
+      for (int i : order)
+        if (spec_nb(frames[i].K) == nb)
+          for (int t = 0; t < rows(frames[i].L, fm::kSpecAngles); ++t) items.push_back({i, t, 0, 0});
+      add(p->spec, kSpec, 0, nb, b0);
+    }
+  } else {
     b0 = begin();
     for (int i : order)
-      if (spec_nb(frames[i].K) == nb)
-        for (int t = 0; t < rows(frames[i].L, fm::kSpecAngles); ++t) items.push_back({i, t, 0, 0});
-    add(p->spec, kSpec, 0, nb, b0);
+      for (int t = 0; t < rows(frames[i].K * frames[i].M, 256); ++t) items.push_back({i, t, 0, 0});
+    add(p->spec, kSplit, 0, 0, b0);
+    for (int nb = 1; nb <= 8; ++nb) {
+      const int per = fm::spectrum16_tile_angles(nb);
+      b0 = begin();
+      for (int i : order)
+        if (spec16_nb(frames[i].K) == nb)
+          for (int t = 0; t < rows(frames[i].L, per); ++t) items.push_back({i, t, 0, 0});
+      add(p->spec, kSpec16, 0, nb, b0);
+    }
   }
   b0 = begin();
   for (int i : order)

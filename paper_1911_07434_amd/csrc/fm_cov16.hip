@@ -196,7 +196,7 @@ template <class H, bool kBatched>
 __global__ __launch_bounds__(256) void cov16_kernel(FrameDev single,
                                                     const FrameDev *__restrict__ frames,
                                                     const Item *__restrict__ items) {
-  __shared__ H lds[4 * kTileHalves];
+  __shared__ __attribute__((aligned(16))) H lds[4 * kTileHalves];
   if constexpr (kBatched) {
     const Item it = items[blockIdx.x];
     cov16_tile<H>(frames[it.frame], it.a, it.b, lds);

@@ -48,7 +48,8 @@ struct FrameDev {
   float2 *V;            // [M][n] orthonormal basis fed to the next product
   double2 *part;        // [nchunk][2][n][n] Gram partial sums
   double2 *small;       // small dense scratch, kSmallSlots * npad^2
-  float2 *Uf;           // [M][K] FP32 copy of U_s for the FP32 spectrum pass
+  float2 *Uf;           // FP32 pass: [M][K] FP32 copy of U_s; FP16 pass: scaled
+                        // hi and lo planes [K][M] of (re, im) FP16 pairs
   int *rlist;           // [1 + L]: count, then angles whose FP32 denominator needs FP64
   int nchunk;           // ceil(M / kGramRows)
   int npad;             // n rounded up to even
@@ -111,6 +112,15 @@ hipError_t launch_spec_prep(const FrameDev *frames, const Item *items, int n_ite
                             hipStream_t s);
 hipError_t launch_spectrum(const FrameDev &single, const FrameDev *frames, const Item *items,
                            int n_items, int nb, fm_prec prec, hipStream_t s);
+// compensated FP16 pass: launch_split writes the hi and lo planes of U_s
+// (one workgroup per 256 entries; resets the recompute list), then one
+// spectrum16 launch per class nb = ceil(K / 8) over tiles of
+// spectrum16_tile_angles(nb) angles
+hipError_t launch_split(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, hipStream_t s);
+hipError_t launch_spectrum16(const FrameDev &single, const FrameDev *frames, const Item *items,
+                             int n_items, int nb, hipStream_t s);
+int spectrum16_tile_angles(int nb);
 hipError_t launch_refine(const FrameDev &single, const FrameDev *frames, const Item *items,
                          int n_items, hipStream_t s);
 hipError_t launch_peaks(const FrameDev &single, const FrameDev *frames, const Item *items,

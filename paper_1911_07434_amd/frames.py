@@ -10,7 +10,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import FM_METHOD_PROJECT, FM_METHOD_SAMPLE, FM_RCOND_DEFAULT, fm_frame
+from . import FM_FP16, FM_FP32, FM_METHOD_PROJECT, FM_METHOD_SAMPLE, FM_RCOND_DEFAULT, fm_frame
 
 
 @dataclass
@@ -85,8 +85,10 @@ class DeviceFrame:
 
 
 def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
-    """All four stages of one frame through the single-frame entry points
-    (`prec` is the covariance operand precision; the other stages are FP32)."""
+    """All four stages of one frame through the single-frame entry points, as
+    a plan at precision `prec` runs them: the covariance at `prec`, the
+    subspace in FP32, the spectrum in FP32 (FP32 plan) or with compensated
+    FP16 products (16-bit plan)."""
     s = fr.spec
     ctx.fm_covariance(fr.X, fr.R, prec, stream)
     if s.method == FM_METHOD_PROJECT:
@@ -94,5 +96,6 @@ def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
                                 0, stream)
     else:
         ctx.fm_subspace_sample(fr.R, fr.idx, s.K, fr.Us, fr.sigma, fr.status, s.rcond, stream)
-    ctx.fm_pseudospectrum(fr.Us, s.theta0_deg, s.dtheta_deg, s.L, fr.P, 0, stream)
+    sprec = FM_FP32 if prec == FM_FP32 else FM_FP16
+    ctx.fm_pseudospectrum(fr.Us, s.theta0_deg, s.dtheta_deg, s.L, fr.P, sprec, stream)
     ctx.fm_peaks(fr.P, s.K, fr.peak_idx, fr.peak_val, fr.n_found, stream)

@@ -5,6 +5,8 @@ Bars (written in each test):
     relative Frobenius error <= 1e-6 otherwise (FP32 accumulation);
   * pseudo-spectrum: max |10 log10(P_gpu / P_oracle)| <= 1e-3 dB on the FP32
     path, both for the spectrum stage alone (same U_s bits) and end to end;
+    the compensated FP16 spectrum pass meets the same bar on the same U_s
+    bits; 16-bit plans end to end <= 1e-2 dB;
   * peaks: bit-exact on identical float32 spectra; end to end, every oracle
     peak within one grid step of a GPU peak and the same count;
   * subspace: projector distance small and the spectra of both subspaces
@@ -104,42 +106,56 @@ def test_covariance_leading_dimensions(ctx):
 # stage 3: pseudo-spectrum on the same U_s bits
 # ----------------------------------------------------------------------------
 
-def _spectrum_case(ctx, Us, th0, dth, L):
+SPEC_PRECS = {"fp32": fm.FM_FP32, "fp16": fm.FM_FP16}
+
+
+def _spectrum_case(ctx, Us, th0, dth, L, prec="fp32"):
     K, M = Us.shape
     P = torch.empty(L, dtype=torch.float32, device="cuda")
-    ctx.fm_pseudospectrum(dev(Us), th0, dth, L, P)
+    ctx.fm_pseudospectrum(dev(Us), th0, dth, L, P, prec=SPEC_PRECS[prec])
     torch.cuda.synchronize()
     Po, deno = oracle.pseudospectrum(Us, th0, dth, L, threads=oracle.default_threads())
     return P.cpu().numpy(), Po, deno
 
 
+# The compensated FP16 pass (hi + lo operands, ~22-bit products, FP32
+# accumulation) is held to the FP32 bar as well.
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
 @pytest.mark.parametrize("name", ["c1", "c2"])
-def test_spectrum_on_oracle_subspace(ctx, name):
+def test_spectrum_on_oracle_subspace(ctx, name, prec):
     cfg = fmsynth.CONFIGS[name]
-    say(f"spectrum {name}")
+    say(f"spectrum {name} {prec}")
     fr, _ = fmsynth.config_frame(name, seed=11)
     R = oracle.covariance(fr.X, threads=oracle.default_threads())
     Us, _, _ = oracle.subspace_project(R, fmsynth.make_omega(fr.M, cfg["l"], 11), cfg["q"], fr.K)
     th0, dth, L = fmsynth.grid(cfg["L"])
-    Pg, Po, _ = _spectrum_case(ctx, Us, th0, dth, L)
+    Pg, Po, _ = _spectrum_case(ctx, Us, th0, dth, L, prec)
+    say(f"  max |dP| = {db_err(Pg, Po):.3g} dB")
     assert db_err(Pg, Po) <= DB_FP32
 
 
-@pytest.mark.parametrize("M,K,L", [(2, 1, 7), (17, 5, 333), (100, 33, 1000), (256, 64, 4097)])
-def test_spectrum_random_orthonormal(ctx, M, K, L):
+# K spans every row-block class of both passes; M and L leave ragged chunks
+# and angle tiles
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("M,K,L", [(2, 1, 7), (17, 5, 333), (100, 33, 1000), (256, 64, 4097),
+                                   (1000, 8, 2049), (77, 9, 515), (300, 16, 700),
+                                   (129, 17, 257), (64, 24, 1025), (96, 40, 999),
+                                   (200, 48, 321), (150, 57, 130)])
+def test_spectrum_random_orthonormal(ctx, M, K, L, prec):
     rng = np.random.default_rng(M + K)
     Q, _ = np.linalg.qr(rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K)))
     th0, dth = -80.0, 160.0 / max(L - 1, 1)
-    Pg, Po, _ = _spectrum_case(ctx, np.ascontiguousarray(Q.T), th0, dth, L)
+    Pg, Po, _ = _spectrum_case(ctx, np.ascontiguousarray(Q.T), th0, dth, L, prec)
     assert db_err(Pg, Po) <= DB_FP32
 
 
-def test_spectrum_single_source_pole_and_dirichlet(ctx):
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_spectrum_single_source_pole_and_dirichlet(ctx, prec):
     M, L = 512, 18001
     th0, dth, _ = fmsynth.grid(L)
     l0 = 12345
     a0 = fmsynth.steering_matrix(M, [th0 + l0 * dth])[:, 0]
-    Pg, Po, _ = _spectrum_case(ctx, (a0 / np.sqrt(M))[None, :], th0, dth, L)
+    Pg, Po, _ = _spectrum_case(ctx, (a0 / np.sqrt(M))[None, :], th0, dth, L, prec)
     assert int(np.argmax(Pg)) == l0
     ok = np.abs(np.arange(L) - l0) > 0
     assert db_err(Pg[ok], Po[ok]) <= DB_FP32
@@ -391,6 +407,9 @@ def test_argument_validation(ctx):
     assert e.value.status == fm.FM_E_ARG
     with pytest.raises(fm.FmError) as e:
         ctx.fm_subspace_project(R, Om, 2, 3, Us, sig, st, prec=fm.FM_BF16)  # FP32 only
+    assert e.value.status == fm.FM_E_UNSUPPORTED
+    with pytest.raises(fm.FmError) as e:
+        ctx.fm_pseudospectrum(Us, 0.0, 1.0, 10, P, prec=fm.FM_BF16)  # FP32 or FP16 only
     assert e.value.status == fm.FM_E_UNSUPPORTED
     small = fm.Context(0, 1024)
     with pytest.raises(fm.FmError) as e:
