@@ -102,6 +102,77 @@ def serve_legs(ctx, fm, torch, seconds, seed):
     return res
 
 
+def uneven_leg(fm, torch, stream, seed, steps, tune_cache=None):
+    """The uneven-batch workload: 512 frames with M from {256, 512, 1024,
+    2048}, T ~ U[M/2, 2M], K ~ U[1, 16], SNR ~ U[-5, 20] dB, Method 2 with
+    l = K + 8 and q = 2, 18001-angle grid, all in one plan replayed as one
+    graph launch.  Timed with the built-in kernel variants, then again after
+    the autotuner has chosen variants on these frames (results checked
+    bit-identical)."""
+    import fmsynth
+    from paper_1911_07434_amd import autotune
+    from paper_1911_07434_amd.frames import DeviceFrame, FrameSpec
+    shapes = fmsynth.uneven_batch(512, seed)
+    th0, dth, L = fmsynth.grid(18001)
+    t0 = time.time()
+    frames = []
+    for sh in shapes:
+        X, _ = fmsynth.make_batch_device(sh["M"], sh["T"], sh["K"], sh["snr_db"], 1, sh["seed"])
+        Om = fmsynth.make_omega_device(sh["M"], sh["l"], 1, sh["seed"])
+        spec = FrameSpec(M=sh["M"], T=sh["T"], K=sh["K"], n=sh["l"], q=sh["q"], L=L,
+                         theta0_deg=th0, dtheta_deg=dth)
+        frames.append(DeviceFrame(spec, X=X[0], rnd=Om[0]))
+    torch.cuda.synchronize()
+    flops = sum(cov_flops(s["M"], s["T"]) for s in shapes)
+    log(f"uneven batch: 512 frames generated in {time.time() - t0:.1f} s, "
+        f"covariance {flops / 1e12:.2f} TFLOP per batch")
+    descs = [d.descriptor() for d in frames]
+
+    def timed(plan, n):
+        with torch.cuda.stream(stream):
+            plan.run(use_graph=True, stream=stream)
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(n)]
+            for a, b in ev:
+                a.record(stream)
+                plan.run(use_graph=True, stream=stream)
+                b.record(stream)
+            torch.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        return {"frames_per_s": round(512.0 / (float(np.median(ms)) * 1e-3), 1),
+                "ms_per_launch": {"p10": round(float(np.percentile(ms, 10)), 3),
+                                  "p50": round(float(np.median(ms)), 3),
+                                  "p90": round(float(np.percentile(ms, 90)), 3)}}
+
+    res = {"frames": 512, "launch": "one hipGraph per batch (all stages, all frames)",
+           "covariance_tflop_per_batch": round(flops / 1e12, 3),
+           "mean_K": round(float(np.mean([s["K"] for s in shapes])), 2)}
+    for pname, prec in (("fp32", fm.FM_FP32), ("fp16", fm.FM_FP16)):
+        c = fm.Context(0, 1 << 20)           # built-in variants
+        plan = fm.Plan(c, descs, prec=prec)
+        base = timed(plan, steps)
+        ref = [frames[i].P.cpu().numpy() for i in range(0, 512, 37)]
+        plan.close()
+        table = autotune.tune(c, frames, prec, reps=3, max_frames=64, stream=stream, log=log)
+        if tune_cache:
+            key = autotune.cache_key(torch.cuda.get_device_name(0), autotune.library_id(), prec)
+            autotune.save(tune_cache, key, table)
+        plan = fm.Plan(c, descs, prec=prec)
+        tuned = timed(plan, steps)
+        same = all(np.array_equal(r, frames[i].P.cpu().numpy())
+                   for r, i in zip(ref, range(0, 512, 37)))
+        plan.close()
+        c.close()
+        res[pname] = {"builtin": base, "autotuned": tuned, "tuned_bitwise_equal": bool(same),
+                      "knobs": autotune.to_json(table)}
+        log(f"uneven {pname}: built-in {base['frames_per_s']} frames/s, autotuned "
+            f"{tuned['frames_per_s']} frames/s, bitwise equal {same}")
+    del frames
+    torch.cuda.empty_cache()
+    return res
+
+
 def _plain_music_executor():
     from paper_1911_07434_amd.serve import GpuExecutor
 
@@ -160,6 +231,10 @@ def main():
                     help="covariance operand precision of the main timed step")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the Poisson arrival trace of the serving leg (0 = skip)")
+    ap.add_argument("--uneven-steps", type=int, default=5,
+                    help="timed graph launches of the 512-frame uneven batch (0 = skip)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file to store the autotuner's choices in")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -246,6 +321,7 @@ def main():
         elapsed = time.perf_counter() - t0
     stage_ms = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs]))
                 for i, n in enumerate(stage_names)}
+    step_ms = np.array([e[0].elapsed_time(e[4]) for e in evs])
     ms_per_step = elapsed * 1e3 / args.steps
     value = B / (elapsed / args.steps)
     st = np.array([int(d.status.cpu()[0]) for d in frames2[:8]])
@@ -276,6 +352,9 @@ def main():
                    "L": L_GRID, "parallelism": "single GPU, frames batched per launch"},
         "angles_per_s": round(value * K, 1),
         "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
+        "step_ms_events": {"p10": round(float(np.percentile(step_ms, 10)), 3),
+                           "p50": round(float(np.median(step_ms)), 3),
+                           "p90": round(float(np.percentile(step_ms, 90)), 3)},
         "roofline": roofline,
     }
 
@@ -306,8 +385,10 @@ def main():
             del planm
         out["mixed_precision"] = mixed
         out["mixed_precision_note"] = ("covariance operands in FP16/BF16 with FP32 "
-                                       "accumulation; sketch and spectrum FP32; small dense "
-                                       "steps and peak-region denominators FP64")
+                                       "accumulation; sketch FP32; spectrum on FP16 matrix "
+                                       "cores with hi+lo split operands (three products, FP32 "
+                                       "accumulation); small dense steps and peak-region "
+                                       "denominators FP64")
 
         # ---- Method 1 on the same frames -----------------------------------
         del plan2
@@ -373,6 +454,11 @@ def main():
         }
         out["frame_latency_ms_alone"] = {"p50": round(float(np.percentile(lat, 50)), 3),
                                          "p99": round(float(np.percentile(lat, 99)), 3)}
+
+    # ---- uneven batch in one graph launch, built-in vs autotuned variants ---
+    if not args.no_extra and args.uneven_steps > 0:
+        out["uneven_batch"] = uneven_leg(fm, torch, stream, args.seed + 7, args.uneven_steps,
+                                         args.tune_cache)
 
     # ---- serving: Poisson arrivals of mixed-shape frames ---------------------
     if not args.no_extra and args.serve_seconds > 0:

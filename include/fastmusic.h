@@ -275,6 +275,37 @@ fm_status fm_plan_peaks(fm_plan *plan, void *stream);
  * HIP graph (on the first call for a given stream) and replayed afterwards. */
 fm_status fm_plan_run(fm_plan *plan, void *stream, int use_graph);
 
+/* ------------------------------------------------------------------------ */
+/* tuning: kernel variants per shape bucket                                 */
+/* ------------------------------------------------------------------------ */
+
+/* A knob selects one of several kernel variants for a shape bucket.  All
+ * variants of a knob compute bit-identical results; only their speed
+ * differs with the shapes of the batch.  A context starts with built-in
+ * defaults; an autotuner times the variants on the caller's frames and
+ * installs its choices with fm_set_knob.  Plans built afterwards, and
+ * single-frame calls, use the context's current values (a plan keeps the
+ * values it was built with).
+ *   FM_KNOB_COV_SCHEDULE   bucket = log2(M) - 7 clamped to [0, 5]
+ *                          (M <= 128, 256, 512, 1024, 2048, >= 4096).
+ *                          0: all covariance tiles of a frame go to one XCD
+ *                          (one L2 holds its snapshots); 1: the frame's tiles
+ *                          are dealt one by one to the least-loaded XCD.
+ *   FM_KNOB_SPEC_ANGLES    bucket = ceil(K/8) - 1 (0..7).  Angles per
+ *                          workgroup of the FP32 spectrum pass: 64, 128, or
+ *                          256 (buckets 0..3 only).
+ *   FM_KNOB_SPEC16_ANGLES  the same for the compensated FP16 spectrum pass. */
+typedef enum {
+  FM_KNOB_COV_SCHEDULE = 0,
+  FM_KNOB_SPEC_ANGLES = 1,
+  FM_KNOB_SPEC16_ANGLES = 2
+} fm_knob;
+
+/* FM_E_ARG (with a message) for an unknown knob, bucket or value. */
+fm_status fm_set_knob(fm_ctx *ctx, int knob, int bucket, int value);
+/* Current value, or -1 for an unknown knob or bucket. */
+int fm_get_knob(const fm_ctx *ctx, int knob, int bucket);
+
 #ifdef __cplusplus
 }
 #endif

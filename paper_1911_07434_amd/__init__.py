@@ -22,6 +22,7 @@ FM_METHOD_PROJECT, FM_METHOD_SAMPLE = 0, 1
 FM_ST_NONFINITE, FM_ST_EIG_MAXIT, FM_ST_RANK_DEFICIENT, FM_ST_FEW_PEAKS, FM_ST_BAD_INDEX = (
     1, 4, 8, 16, 32)
 FM_RCOND_DEFAULT = 1e-6
+FM_KNOB_COV_SCHEDULE, FM_KNOB_SPEC_ANGLES, FM_KNOB_SPEC16_ANGLES = 0, 1, 2
 
 # every symbol of include/fastmusic.h
 EXPORTS = (
@@ -29,7 +30,7 @@ EXPORTS = (
     "fm_covariance", "fm_subspace_sample", "fm_subspace_project", "fm_pseudospectrum",
     "fm_peaks", "fm_plan_create", "fm_plan_destroy", "fm_plan_workspace_bytes",
     "fm_plan_covariance", "fm_plan_subspace", "fm_plan_pseudospectrum", "fm_plan_peaks",
-    "fm_plan_run", "fm_plan_bytes", "fm_plan_create_in",
+    "fm_plan_run", "fm_plan_bytes", "fm_plan_create_in", "fm_set_knob", "fm_get_knob",
 )
 
 
@@ -89,6 +90,8 @@ def load_library(path: str = LIB_PATH):
         "fm_plan_run": ([P, P, I], I),
         "fm_plan_bytes": ([P, C.POINTER(fm_frame), I, I], Z),
         "fm_plan_create_in": ([P, C.POINTER(fm_frame), I, I, P, Z, P, C.POINTER(P)], I),
+        "fm_set_knob": ([P, I, I, I], I),
+        "fm_get_knob": ([P, I, I], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -133,6 +136,14 @@ class Context:
     def check(self, st: int):
         if st != FM_OK:
             raise FmError(st, self.lib.fm_last_error(self.h).decode())
+
+    # -- tuning knobs ---------------------------------------------------------
+
+    def set_knob(self, knob: int, bucket: int, value: int):
+        self.check(self.lib.fm_set_knob(self.h, knob, bucket, value))
+
+    def get_knob(self, knob: int, bucket: int) -> int:
+        return self.lib.fm_get_knob(self.h, knob, bucket)
 
     # -- single-frame stages (device tensors in, device tensors out) --------
 

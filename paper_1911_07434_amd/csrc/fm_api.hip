@@ -16,12 +16,44 @@
 using fm::FrameDev;
 using fm::Item;
 
+// tuning knobs: kernel variants per shape bucket (every variant computes
+// bit-identical results)
+constexpr int kKnobs = 3, kBuckets = 8;
+
 struct fm_ctx {
   int device = 0;
   char *arena = nullptr;
   size_t arena_bytes = 0;
   std::string err;
+  int knob[kKnobs][kBuckets];
 };
+
+namespace {
+
+int knob_buckets(int knob) { return knob == FM_KNOB_COV_SCHEDULE ? 6 : 8; }
+
+bool knob_value_ok(int knob, int bucket, int v) {
+  if (knob == FM_KNOB_COV_SCHEDULE) return v == 0 || v == 1;
+  // spectrum angle tiles: 64 nnb angles, nnb = 4 only for row-block classes <= 4
+  return v == 64 || v == 128 || (v == 256 && bucket < 4);
+}
+
+int knob_default(int knob, int bucket) {
+  switch (knob) {
+    case FM_KNOB_COV_SCHEDULE: return 0;
+    case FM_KNOB_SPEC_ANGLES: return 64;
+    default: return bucket < 2 ? 256 : (bucket < 6 ? 128 : 64);
+  }
+}
+
+// bucket of a covariance frame: log2(M) - 7 clamped to [0, 5]
+int cov_bucket(int M) {
+  int b = 0;
+  while (b < 5 && (128 << b) < M) ++b;
+  return b;
+}
+
+}  // namespace
 
 struct fm_plan {
   fm_ctx *ctx = nullptr;
@@ -176,8 +208,8 @@ fm_status check_peaks(fm_ctx *c, const void *P, int L, int K, const void *idx, c
 }
 
 // MFMA row/column block classes (one kernel instantiation per class)
-int spec_nb(int K) { return (2 * K + 15) / 16; }
-int spec16_nb(int K) { return (K + 7) / 8; }
+// row-block class of both spectrum passes: ceil(2K / 16) = ceil(K / 8)
+int spec_nb(int K) { return (K + 7) / 8; }
 int sketch_nb(int n) { return (2 * n + 31) / 32; }
 
 // ---------------------------------------------------------------------------
@@ -255,6 +287,8 @@ FM_API fm_status fm_create(int device, size_t workspace_bytes, fm_ctx **out) {
   fm_ctx *c = new (std::nothrow) fm_ctx;
   if (!c) return FM_E_WORKSPACE;
   c->device = device;
+  for (int k = 0; k < kKnobs; ++k)
+    for (int b = 0; b < kBuckets; ++b) c->knob[k][b] = knob_default(k, b);
   c->arena_bytes = workspace_bytes ? workspace_bytes : (size_t)64 << 20;
   if (hipSetDevice(device) != hipSuccess ||
       hipMalloc((void **)&c->arena, c->arena_bytes) != hipSuccess) {
@@ -277,6 +311,23 @@ FM_API fm_status fm_destroy(fm_ctx *ctx) {
 // ===========================================================================
 // single-frame stages
 // ===========================================================================
+
+FM_API fm_status fm_set_knob(fm_ctx *ctx, int knob, int bucket, int value) {
+  if (!ctx) return FM_E_ARG;
+  if (knob < 0 || knob >= kKnobs) return fail(ctx, FM_E_ARG, "set_knob: unknown knob %d", knob);
+  if (bucket < 0 || bucket >= knob_buckets(knob))
+    return fail(ctx, FM_E_ARG, "set_knob: knob %d has no bucket %d", knob, bucket);
+  if (!knob_value_ok(knob, bucket, value))
+    return fail(ctx, FM_E_ARG, "set_knob: value %d not valid for knob %d bucket %d", value, knob,
+                bucket);
+  ctx->knob[knob][bucket] = value;
+  return FM_OK;
+}
+
+FM_API int fm_get_knob(const fm_ctx *ctx, int knob, int bucket) {
+  if (!ctx || knob < 0 || knob >= kKnobs || bucket < 0 || bucket >= knob_buckets(knob)) return -1;
+  return ctx->knob[knob][bucket];
+}
 
 FM_API fm_status fm_covariance(fm_ctx *ctx, void *stream, const void *X, int M, int T,
                                int64_t ldx, void *R, int64_t ldr, fm_prec prec) {
@@ -370,12 +421,15 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
   f.dtheta = dtheta_deg;
   f.P = P;
   hipStream_t s = (hipStream_t)stream;
+  const int nb = spec_nb(K);
   if (prec == FM_FP32) {
+    const int nnb = ctx->knob[FM_KNOB_SPEC_ANGLES][nb - 1] / 64;
     FM_CHECK_LAUNCH(ctx, fm::launch_uf(f, s));
-    FM_CHECK_LAUNCH(ctx, fm::launch_spectrum(f, nullptr, nullptr, 0, spec_nb(K), prec, s));
+    FM_CHECK_LAUNCH(ctx, fm::launch_spectrum(f, nullptr, nullptr, 0, nb, nnb, s));
   } else {
+    const int nnb = ctx->knob[FM_KNOB_SPEC16_ANGLES][nb - 1] / 64;
     FM_CHECK_LAUNCH(ctx, fm::launch_split(f, nullptr, nullptr, 0, s));
-    FM_CHECK_LAUNCH(ctx, fm::launch_spectrum16(f, nullptr, nullptr, 0, spec16_nb(K), s));
+    FM_CHECK_LAUNCH(ctx, fm::launch_spectrum16(f, nullptr, nullptr, 0, nb, nnb, s));
   }
   FM_CHECK_LAUNCH(ctx, fm::launch_refine(f, nullptr, nullptr, 0, s));
   return FM_OK;
@@ -419,9 +473,9 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kSmall: return fm::launch_small(cls, fr, it, L.count, L.mode, s);
     case kApply: return fm::launch_apply(cls, fr, it, L.count, L.mode, s);
     case kSpecPrep: return fm::launch_spec_prep(fr, it, L.count, s);
-    case kSpec: return fm::launch_spectrum(cls, fr, it, L.count, L.n_class, FM_FP32, s);
+    case kSpec: return fm::launch_spectrum(cls, fr, it, L.count, L.n_class, L.mode, s);
     case kSplit: return fm::launch_split(cls, fr, it, L.count, s);
-    case kSpec16: return fm::launch_spectrum16(cls, fr, it, L.count, L.n_class, s);
+    case kSpec16: return fm::launch_spectrum16(cls, fr, it, L.count, L.n_class, L.mode, s);
     case kRefine: return fm::launch_refine(cls, fr, it, L.count, s);
     case kPeaks: return fm::launch_peaks(cls, fr, it, L.count, s);
   }
@@ -545,18 +599,32 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   // w mod 8, each XCD with its own L2.  Frames are dealt to the 8 XCDs
   // (largest first onto the least loaded) and position w of the list takes
   // the next tile of XCD (w mod 8)'s frames, so all tiles of a frame share
-  // one L2 and each window of its snapshots is fetched once per XCD.
+  // one L2 and each window of its snapshots is fetched once per XCD.  With
+  // the schedule knob at 1 for a frame's M bucket, its tiles are dealt one
+  // by one instead (a frame whose snapshots overflow one L2 gains nothing
+  // from grouping and loses balance).
   size_t b0 = begin();
   {
     constexpr int kXcd = 8;
     std::vector<std::vector<Item>> q(kXcd);
     std::vector<double> load(kXcd, 0.0);
     for (int i : order) {
-      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
       const int nt = (frames[i].M + fm::kCovTile - 1) / fm::kCovTile;
-      load[x] += (double)nt * (nt + 1) / 2 * frames[i].T;
-      for (int ti = 0; ti < nt; ++ti)
-        for (int tj = 0; tj <= ti; ++tj) q[x].push_back({i, ti, tj, 0});
+      if (ctx->knob[FM_KNOB_COV_SCHEDULE][cov_bucket(frames[i].M)] == 0) {
+        // the whole frame onto the least-loaded XCD
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[x] += (double)nt * (nt + 1) / 2 * frames[i].T;
+        for (int ti = 0; ti < nt; ++ti)
+          for (int tj = 0; tj <= ti; ++tj) q[x].push_back({i, ti, tj, 0});
+      } else {
+        // each tile onto the least-loaded XCD
+        for (int ti = 0; ti < nt; ++ti)
+          for (int tj = 0; tj <= ti; ++tj) {
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[x] += frames[i].T;
+            q[x].push_back({i, ti, tj, 0});
+          }
+      }
     }
     std::vector<size_t> pos(kXcd, 0);
     size_t left = 0;
@@ -652,25 +720,21 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     b0 = begin();
     for (int i : order) items.push_back({i, 0, 0, 0});
     add(p->spec, kSpecPrep, 0, 0, b0);
-    for (int nb = 1; nb <= 8; ++nb) {
-      b0 = begin();
-      for (int i : order)
-        if (spec_nb(frames[i].K) == nb)
-          for (int t = 0; t < rows(frames[i].L, fm::kSpecAngles); ++t) items.push_back({i, t, 0, 0});
-      add(p->spec, kSpec, 0, nb, b0);
-    }
   } else {
     b0 = begin();
     for (int i : order)
       for (int t = 0; t < rows(frames[i].K * frames[i].M, 256); ++t) items.push_back({i, t, 0, 0});
     add(p->spec, kSplit, 0, 0, b0);
+  }
+  {
+    const int knob = prec == FM_FP32 ? FM_KNOB_SPEC_ANGLES : FM_KNOB_SPEC16_ANGLES;
     for (int nb = 1; nb <= 8; ++nb) {
-      const int per = fm::spectrum16_tile_angles(nb);
+      const int per = ctx->knob[knob][nb - 1];
       b0 = begin();
       for (int i : order)
-        if (spec16_nb(frames[i].K) == nb)
+        if (spec_nb(frames[i].K) == nb)
           for (int t = 0; t < rows(frames[i].L, per); ++t) items.push_back({i, t, 0, 0});
-      add(p->spec, kSpec16, 0, nb, b0);
+      add(p->spec, prec == FM_FP32 ? kSpec : kSpec16, per / 64, nb, b0);
     }
   }
   b0 = begin();

@@ -65,7 +65,6 @@ constexpr int kSmallSlots = 8;     // npad^2 complex128 matrices per frame
 constexpr int kCovTile = 128;      // covariance tile edge (complex entries)
 constexpr int kSketchRows = 128;   // rows of R per sketch workgroup
 constexpr int kApplyRows = 64;     // rows per apply / gather workgroup
-constexpr int kSpecAngles = 64;    // angles per spectrum workgroup
 constexpr int kSpecChunk = 64;     // channels of U_s staged in LDS per step
 constexpr int kRefineGroups = 4;   // FP64 recompute workgroups per frame
 constexpr int kMaxL = 64;          // max sketch width of Method 2 (l)
@@ -106,21 +105,19 @@ hipError_t launch_apply(const FrameDev &single, const FrameDev *frames, const It
 hipError_t launch_uf(const FrameDev &single, hipStream_t s);
 // spectrum stage = prep (reset the recompute lists; batched only -- the
 // single-frame path resets it in launch_uf), the FP32 pass (one launch per
-// row-block class nb = ceil(2K/16), passed in single.K for batched launches)
-// and the FP64 recompute of the listed angles
+// row-block class nb = ceil(K / 8); tiles of 64 nnb angles, nnb in {1, 2}
+// and also 4 for nb <= 4) and the FP64 recompute of the listed angles
 hipError_t launch_spec_prep(const FrameDev *frames, const Item *items, int n_items,
                             hipStream_t s);
 hipError_t launch_spectrum(const FrameDev &single, const FrameDev *frames, const Item *items,
-                           int n_items, int nb, fm_prec prec, hipStream_t s);
+                           int n_items, int nb, int nnb, hipStream_t s);
 // compensated FP16 pass: launch_split writes the hi and lo planes of U_s
 // (one workgroup per 256 entries; resets the recompute list), then one
-// spectrum16 launch per class nb = ceil(K / 8) over tiles of
-// spectrum16_tile_angles(nb) angles
+// spectrum16 launch per class nb = ceil(K / 8) over tiles of 64 nnb angles
 hipError_t launch_split(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, hipStream_t s);
 hipError_t launch_spectrum16(const FrameDev &single, const FrameDev *frames, const Item *items,
-                             int n_items, int nb, hipStream_t s);
-int spectrum16_tile_angles(int nb);
+                             int n_items, int nb, int nnb, hipStream_t s);
 hipError_t launch_refine(const FrameDev &single, const FrameDev *frames, const Item *items,
                          int n_items, hipStream_t s);
 hipError_t launch_peaks(const FrameDev &single, const FrameDev *frames, const Item *items,

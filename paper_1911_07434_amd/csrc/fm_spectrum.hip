@@ -69,7 +69,7 @@ __device__ double den_fp64(const FrameDev &f, unsigned long long F, int lane) {
           acc[k].y = fma(u.x, a.y, fma(-u.y, a.x, acc[k].y));
         }
       }
-      a = make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+      a = make_double2(fma(a.x, w.x, -(a.y * w.y)), fma(a.x, w.y, a.y * w.x));
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -85,11 +85,13 @@ __device__ double den_fp64(const FrameDev &f, unsigned long long F, int lane) {
   return (double)M - proj;
 }
 
-// FP32 pass over one tile of kSpecAngles angles (four waves of 16).  U_s is
+// FP32 pass over one tile of 64 NNB angles (four waves of 16 NNB).  U_s is
 // staged through LDS in chunks of kSpecChunk channels, double buffered: the
 // next chunk's global loads are in flight while the matrix cores work on
-// the current one.  NB = row blocks of 16 over the 2K stacked outputs.
-template <int NB>
+// the current one.  NB = row blocks of 16 over the 2K stacked outputs; each
+// U_s operand read from LDS feeds the NNB angle blocks of the wave.  An
+// angle's arithmetic does not depend on NNB.
+template <int NB, int NNB>
 __device__ __forceinline__ void spectrum_tile(const FrameDev &f, int tile, const float2 *tab,
                                               float2 (*ubuf)[kSpecChunk * 8 * NB]) {
   const int tid = threadIdx.x;
@@ -97,8 +99,11 @@ __device__ __forceinline__ void spectrum_tile(const FrameDev &f, int tile, const
   const int wave = tid >> 6;
   const int n = lane & 15, r = lane >> 4;
   const int M = f.M, K = f.K, L = f.L;
-  const int gl = tile * kSpecAngles + wave * 16 + n;
-  const unsigned long long F = turn_freq(f.theta0, f.dtheta, min(gl, L - 1));
+  const int first = tile * (64 * NNB) + wave * (16 * NNB);
+  unsigned long long F[NNB];
+#pragma unroll
+  for (int nb = 0; nb < NNB; ++nb)
+    F[nb] = turn_freq(f.theta0, f.dtheta, min(first + 16 * nb + n, L - 1));
 
   int kk[NB], part[NB];
   bool okr[NB];
@@ -109,9 +114,11 @@ __device__ __forceinline__ void spectrum_tile(const FrameDev &f, int tile, const
     part[b] = row < K ? 0 : 1;
     kk[b] = okr[b] ? (row < K ? row : row - K) : 0;
   }
-  floatx4 acc[NB];
+  floatx4 acc[NB][NNB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int nb = 0; nb < NNB; ++nb) acc[b][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   // cooperative chunk loads: kSpecChunk * K float2, at most 2 * NB per thread
   const int chunk_elems = kSpecChunk * K;
@@ -136,9 +143,10 @@ __device__ __forceinline__ void spectrum_tile(const FrameDev &f, int tile, const
   load_chunk(0);
   store_chunk(0);
   __syncthreads();  // publishes the first chunk and the phasor table
-  const float2 w4 = phasor32(4u, F, tab);
+  float2 w4[NNB], ph[NNB];
+#pragma unroll
+  for (int nb = 0; nb < NNB; ++nb) w4[nb] = phasor32(4u, F[nb], tab);
 
-  float2 ph = make_float2(1.f, 0.f);
   for (int c = 0; c < nchunk; ++c) {
     const bool more = c + 1 < nchunk;
     if (more) load_chunk(c + 1);
@@ -146,39 +154,48 @@ __device__ __forceinline__ void spectrum_tile(const FrameDev &f, int tile, const
 #pragma unroll 4
     for (int s = 0; s < kSpecChunk / 4; ++s) {
       const int m = c * kSpecChunk + 4 * s + r;
-      ph = (s == 0) ? phasor32((unsigned)m, F, tab) : cmulf(ph, w4);
+#pragma unroll
+      for (int nb = 0; nb < NNB; ++nb)
+        ph[nb] = (s == 0) ? phasor32((unsigned)m, F[nb], tab) : cmulf(ph[nb], w4[nb]);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const float2 u = okr[b] ? ub[(4 * s + r) * K + kk[b]] : make_float2(0.f, 0.f);
         const float a1 = part[b] == 0 ? u.x : -u.y;
         const float a2 = part[b] == 0 ? u.y : u.x;
-        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, ph.x, acc[b], 0, 0, 0);
-        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, ph.y, acc[b], 0, 0, 0);
+#pragma unroll
+        for (int nb = 0; nb < NNB; ++nb) {
+          acc[b][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, ph[nb].x, acc[b][nb], 0, 0, 0);
+          acc[b][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, ph[nb].y, acc[b][nb], 0, 0, 0);
+        }
       }
     }
     if (more) store_chunk((c + 1) & 1);
     __syncthreads();
   }
-  float ss = 0.f;
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
+  for (int nb = 0; nb < NNB; ++nb) {
+    float ss = 0.f;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) ss = fmaf(acc[b][v], acc[b][v], ss);
-  ss += __shfl_xor(ss, 16);
-  ss += __shfl_xor(ss, 32);
-  if (r == 0 && gl < L) {
-    const float den32 = (float)M - ss;
-    const float floor32 = (float)M * 5.9604644775390625e-08f;  // M * 2^-24
-    f.P[gl] = 1.0f / fmaxf(den32, floor32);
-    // main lobes, where M - ||U^H a||^2 cancels, are recomputed in FP64
-    if (den32 < (float)M * 0.0625f) {
-      const int slot = atomicAdd(f.rlist, 1);
-      f.rlist[1 + slot] = gl;
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ss = fmaf(acc[b][nb][v], acc[b][nb][v], ss);
+    ss += __shfl_xor(ss, 16);
+    ss += __shfl_xor(ss, 32);
+    const int gl = first + 16 * nb + n;
+    if (r == 0 && gl < L) {
+      const float den32 = (float)M - ss;
+      const float floor32 = (float)M * 5.9604644775390625e-08f;  // M * 2^-24
+      f.P[gl] = 1.0f / fmaxf(den32, floor32);
+      // main lobes, where M - ||U^H a||^2 cancels, are recomputed in FP64
+      if (den32 < (float)M * 0.0625f) {
+        const int slot = atomicAdd(f.rlist, 1);
+        f.rlist[1 + slot] = gl;
+      }
     }
   }
 }
 
-template <int NB, bool kBatched>
+template <int NB, int NNB, bool kBatched>
 __global__ __launch_bounds__(256) void spectrum_kernel(FrameDev single, const FrameDev *frames,
                                                        const Item *items) {
   __shared__ float2 tab[256];
@@ -191,7 +208,7 @@ __global__ __launch_bounds__(256) void spectrum_kernel(FrameDev single, const Fr
   // (the first __syncthreads in spectrum_tile also publishes the table)
   int tile;
   const FrameDev &f = spec_frame<kBatched>(single, frames, items, tile);
-  spectrum_tile<NB>(f, tile, tab, ubuf);
+  spectrum_tile<NB, NNB>(f, tile, tab, ubuf);
 }
 
 // FP64 recompute of the listed angles: one wave per angle, the frame's
@@ -231,18 +248,28 @@ __global__ __launch_bounds__(256) void uf_kernel(FrameDev f) {
   f.Uf[e] = make_float2((float)u.x, (float)u.y);
 }
 
-template <int NB>
+template <int NB, int NNB>
 hipError_t launch_nb(const FrameDev &single, const FrameDev *frames, const Item *items,
                      int n_items, hipStream_t s) {
   if (items) {
-    hipLaunchKernelGGL((spectrum_kernel<NB, true>), dim3(n_items), dim3(256), 0, s, single,
+    hipLaunchKernelGGL((spectrum_kernel<NB, NNB, true>), dim3(n_items), dim3(256), 0, s, single,
                        frames, items);
   } else {
-    const int tiles = (single.L + kSpecAngles - 1) / kSpecAngles;
-    hipLaunchKernelGGL((spectrum_kernel<NB, false>), dim3(tiles), dim3(256), 0, s, single,
+    const int tiles = (single.L + 64 * NNB - 1) / (64 * NNB);
+    hipLaunchKernelGGL((spectrum_kernel<NB, NNB, false>), dim3(tiles), dim3(256), 0, s, single,
                        frames, items);
   }
   return hipGetLastError();
+}
+
+template <int NB>
+hipError_t launch_nnb(const FrameDev &single, const FrameDev *frames, const Item *items,
+                      int n_items, int nnb, hipStream_t s) {
+  if constexpr (NB <= 4) {
+    if (nnb == 4) return launch_nb<NB, 4>(single, frames, items, n_items, s);
+  }
+  if (nnb == 2) return launch_nb<NB, 2>(single, frames, items, n_items, s);
+  return launch_nb<NB, 1>(single, frames, items, n_items, s);
 }
 
 }  // namespace
@@ -262,17 +289,16 @@ hipError_t launch_spec_prep(const FrameDev *frames, const Item *items, int n_ite
 }
 
 hipError_t launch_spectrum(const FrameDev &single, const FrameDev *frames, const Item *items,
-                           int n_items, int nb, fm_prec prec, hipStream_t s) {
-  (void)prec;
+                           int n_items, int nb, int nnb, hipStream_t s) {
   switch (nb) {
-    case 1: return launch_nb<1>(single, frames, items, n_items, s);
-    case 2: return launch_nb<2>(single, frames, items, n_items, s);
-    case 3: return launch_nb<3>(single, frames, items, n_items, s);
-    case 4: return launch_nb<4>(single, frames, items, n_items, s);
-    case 5: return launch_nb<5>(single, frames, items, n_items, s);
-    case 6: return launch_nb<6>(single, frames, items, n_items, s);
-    case 7: return launch_nb<7>(single, frames, items, n_items, s);
-    default: return launch_nb<8>(single, frames, items, n_items, s);
+    case 1: return launch_nnb<1>(single, frames, items, n_items, nnb, s);
+    case 2: return launch_nnb<2>(single, frames, items, n_items, nnb, s);
+    case 3: return launch_nnb<3>(single, frames, items, n_items, nnb, s);
+    case 4: return launch_nnb<4>(single, frames, items, n_items, nnb, s);
+    case 5: return launch_nnb<5>(single, frames, items, n_items, nnb, s);
+    case 6: return launch_nnb<6>(single, frames, items, n_items, nnb, s);
+    case 7: return launch_nnb<7>(single, frames, items, n_items, nnb, s);
+    default: return launch_nnb<8>(single, frames, items, n_items, nnb, s);
   }
 }
 

@@ -38,9 +38,6 @@ constexpr int kRowH2 = kCh + 4;           // LDS row stride in (re, im) pairs, 1
 // LDS per buffer: hi and lo planes of 16 NB rows ((Ur, Ui) and (-Ui, Ur) per source)
 constexpr int plane_h2(int nb) { return 16 * nb * kRowH2; }
 
-// angle blocks of 16 per wave for a row-block class
-constexpr int nnb_of(int nb) { return nb <= 2 ? 4 : (nb <= 6 ? 2 : 1); }
-
 // power of two near sqrt(M): U_s entries scaled to magnitude ~1 in FP16
 __device__ inline float u_scale(int M) { return exp2f(rintf(0.5f * log2f((float)M))); }
 
@@ -226,7 +223,7 @@ __device__ __forceinline__ void spec16_tile(const FrameDev &f, int tile, const f
   }
 }
 
-template <int NB, bool kBatched>
+template <int NB, int NNB, bool kBatched>
 __global__ __launch_bounds__(256) void spectrum16_kernel(FrameDev single, const FrameDev *frames,
                                                          const Item *items) {
   __shared__ float2 tab[256];
@@ -238,7 +235,7 @@ __global__ __launch_bounds__(256) void spectrum16_kernel(FrameDev single, const 
   }
   int tile;
   const FrameDev &f = frame16<kBatched>(single, frames, items, tile);
-  spec16_tile<NB, nnb_of(NB)>(f, tile, tab, lds);
+  spec16_tile<NB, NNB>(f, tile, tab, lds);
 }
 
 // U_s (complex128 [K][M]) -> scaled FP16 hi and lo planes ([K][M] (re, im)
@@ -266,23 +263,31 @@ __global__ __launch_bounds__(256) void split_kernel(FrameDev single, const Frame
   Ul[e] = lo;
 }
 
-template <int NB>
+template <int NB, int NNB>
 hipError_t launch16(const FrameDev &single, const FrameDev *frames, const Item *items,
                     int n_items, hipStream_t s) {
   if (items) {
-    hipLaunchKernelGGL((spectrum16_kernel<NB, true>), dim3(n_items), dim3(256), 0, s, single,
-                       frames, items);
+    hipLaunchKernelGGL((spectrum16_kernel<NB, NNB, true>), dim3(n_items), dim3(256), 0, s,
+                       single, frames, items);
   } else {
-    const int per = 64 * nnb_of(NB);
-    hipLaunchKernelGGL((spectrum16_kernel<NB, false>), dim3((single.L + per - 1) / per),
+    const int per = 64 * NNB;
+    hipLaunchKernelGGL((spectrum16_kernel<NB, NNB, false>), dim3((single.L + per - 1) / per),
                        dim3(256), 0, s, single, frames, items);
   }
   return hipGetLastError();
 }
 
-}  // namespace
+template <int NB>
+hipError_t launch16_nnb(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, int nnb, hipStream_t s) {
+  if constexpr (NB <= 4) {
+    if (nnb == 4) return launch16<NB, 4>(single, frames, items, n_items, s);
+  }
+  if (nnb == 2) return launch16<NB, 2>(single, frames, items, n_items, s);
+  return launch16<NB, 1>(single, frames, items, n_items, s);
+}
 
-int spectrum16_tile_angles(int nb) { return 64 * nnb_of(nb); }
+}  // namespace
 
 hipError_t launch_split(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, hipStream_t s) {
@@ -297,16 +302,16 @@ hipError_t launch_split(const FrameDev &single, const FrameDev *frames, const It
 }
 
 hipError_t launch_spectrum16(const FrameDev &single, const FrameDev *frames, const Item *items,
-                             int n_items, int nb, hipStream_t s) {
+                             int n_items, int nb, int nnb, hipStream_t s) {
   switch (nb) {
-    case 1: return launch16<1>(single, frames, items, n_items, s);
-    case 2: return launch16<2>(single, frames, items, n_items, s);
-    case 3: return launch16<3>(single, frames, items, n_items, s);
-    case 4: return launch16<4>(single, frames, items, n_items, s);
-    case 5: return launch16<5>(single, frames, items, n_items, s);
-    case 6: return launch16<6>(single, frames, items, n_items, s);
-    case 7: return launch16<7>(single, frames, items, n_items, s);
-    default: return launch16<8>(single, frames, items, n_items, s);
+    case 1: return launch16_nnb<1>(single, frames, items, n_items, nnb, s);
+    case 2: return launch16_nnb<2>(single, frames, items, n_items, nnb, s);
+    case 3: return launch16_nnb<3>(single, frames, items, n_items, nnb, s);
+    case 4: return launch16_nnb<4>(single, frames, items, n_items, nnb, s);
+    case 5: return launch16_nnb<5>(single, frames, items, n_items, nnb, s);
+    case 6: return launch16_nnb<6>(single, frames, items, n_items, nnb, s);
+    case 7: return launch16_nnb<7>(single, frames, items, n_items, nnb, s);
+    default: return launch16_nnb<8>(single, frames, items, n_items, nnb, s);
   }
 }
 

@@ -11,7 +11,7 @@ constexpr double kTwo64 = 18446744073709551616.0;
 
 // F = frac(-sin(theta)/2) * 2^64: turns per element as a 64-bit fraction
 __device__ inline unsigned long long turn_freq(double theta0, double dtheta, int l) {
-  const double th = theta0 + (double)l * dtheta;
+  const double th = fma((double)l, dtheta, theta0);
   const double s = sin(th * (3.141592653589793 / 180.0));
   double f = -0.5 * s;
   f = f - floor(f);
@@ -29,7 +29,8 @@ __device__ inline float2 phasor32(unsigned m, unsigned long long F, const float2
   const float c = fmaf(d2, fmaf(d2, 1.0f / 24.0f, -0.5f), 1.0f);
   const float s = d * fmaf(d2, fmaf(d2, 1.0f / 120.0f, -1.0f / 6.0f), 1.0f);
   const float2 t = tab[top >> 24];
-  return make_float2(t.x * c - t.y * s, t.x * s + t.y * c);
+  // explicit fused forms: every kernel variant rounds a phasor identically
+  return make_float2(fmaf(t.x, c, -(t.y * s)), fmaf(t.x, s, t.y * c));
 }
 
 // the same phasor in FP64
@@ -41,8 +42,10 @@ __device__ inline double2 phasor64(unsigned long long m, unsigned long long F) {
   return make_double2(c, s);
 }
 
+// complex product with explicit fused forms (no contraction left to the
+// compiler, so the rounding does not depend on the surrounding code)
 __device__ inline float2 cmulf(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 
 }  // namespace steer

@@ -1,0 +1,160 @@
+"""Uneven batches and the tuning knobs on the GPU.
+
+* every variant of every knob gives bit-identical results (R, U_s, sigma, P,
+  peaks) on an uneven batch, for FP32 and 16-bit plans, with and without the
+  graph launch;
+* the autotuner picks valid variants on the device, installs them, and a
+  plan built afterwards still gives the same bits;
+* frames of the uneven workload (M from {256, 512, 1024, 2048}, T ~ U[M/2,
+  2M], K ~ U[1, 16], l = K + 8, q = 2, 18001-angle grid) match the FP64
+  oracle end to end: <= 1e-3 dB (FP32 plan), <= 1e-2 dB (16-bit plan), every
+  oracle AoA within one grid step.
+"""
+import numpy as np
+import pytest
+
+import fmsynth
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1911_07434_amd as fm  # noqa: E402
+from paper_1911_07434_amd import autotune  # noqa: E402
+from paper_1911_07434_amd.frames import DeviceFrame, FrameSpec  # noqa: E402
+
+
+@pytest.fixture()
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = fm.Context(0, 256 << 20)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _uneven(n, seed, Ms=(128, 256, 512), K_range=(1, 40), L=1801):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        M = int(rng.choice(Ms))
+        T = int(rng.integers(M // 2, 2 * M + 1))
+        K = int(rng.integers(K_range[0], min(K_range[1], M // 4) + 1))
+        l, _p = fmsynth.sketch_sizes(M, K)
+        fr = fmsynth.make_frame(M, T, K, float(rng.uniform(-5, 20)), seed=seed * 1000 + i,
+                                angle_range=(-75.0, 75.0), min_sep=1.0)
+        th0, dth, _ = fmsynth.grid(L)
+        spec = FrameSpec(M=M, T=T, K=K, n=l, q=2, L=L, theta0_deg=th0, dtheta_deg=dth)
+        out.append((spec, fr.X, fmsynth.make_omega(M, l, seed * 1000 + i)))
+    return out
+
+
+def _run(ctx, frames, prec, use_graph=False):
+    devs = [DeviceFrame(s, X=torch.from_numpy(X), rnd=torch.from_numpy(r)) for s, X, r in frames]
+    plan = fm.Plan(ctx, [d.descriptor() for d in devs], prec=prec)
+    plan.run(use_graph=use_graph)
+    torch.cuda.synchronize()
+    plan.close()
+    return [d.results() for d in devs]
+
+
+def _same(a, b):
+    for x, y in zip(a, b):
+        for k in ("R", "Us", "sigma", "P", "peak_idx", "peak_val"):
+            assert np.array_equal(x[k], y[k]), k
+        assert x["status"] == y["status"] and x["n_found"] == y["n_found"]
+
+
+def test_knob_defaults_and_validation(ctx):
+    assert ctx.get_knob(fm.FM_KNOB_COV_SCHEDULE, 0) == 0
+    assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 3) == 64
+    assert ctx.get_knob(fm.FM_KNOB_SPEC16_ANGLES, 0) == 256
+    assert ctx.get_knob(fm.FM_KNOB_COV_SCHEDULE, 6) == -1      # no such bucket
+    assert ctx.get_knob(7, 0) == -1
+    for knob, bucket, value in [(fm.FM_KNOB_COV_SCHEDULE, 0, 2), (fm.FM_KNOB_SPEC_ANGLES, 4, 256),
+                                (fm.FM_KNOB_SPEC16_ANGLES, 0, 96), (fm.FM_KNOB_SPEC_ANGLES, 8, 64),
+                                (3, 0, 0)]:
+        with pytest.raises(fm.FmError) as e:
+            ctx.set_knob(knob, bucket, value)
+        assert e.value.status == fm.FM_E_ARG
+    ctx.set_knob(fm.FM_KNOB_SPEC_ANGLES, 3, 256)
+    assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 3) == 256
+
+
+@pytest.mark.parametrize("prec", [fm.FM_FP32, fm.FM_FP16])
+def test_every_variant_bitwise_identical(ctx, prec):
+    frames = _uneven(16, seed=71)
+    say(f"variants prec={prec}: K = {sorted(s.K for s, _, _ in frames)}")
+    ref = _run(ctx, frames, prec)
+    spec_knob = fm.FM_KNOB_SPEC_ANGLES if prec == fm.FM_FP32 else fm.FM_KNOB_SPEC16_ANGLES
+    for v in (1, 0):
+        for b in range(6):
+            ctx.set_knob(fm.FM_KNOB_COV_SCHEDULE, b, v)
+        for angles in (64, 128, 256):
+            for b in range(8):
+                if angles in autotune.choices(spec_knob, b):
+                    ctx.set_knob(spec_knob, b, angles)
+            say(f"  schedule {v}, angles {angles}")
+            _same(ref, _run(ctx, frames, prec, use_graph=(angles == 128)))
+
+
+def test_autotune_installs_valid_choices_and_keeps_bits(ctx, tmp_path):
+    frames = _uneven(12, seed=72)
+    devs = [DeviceFrame(s, X=torch.from_numpy(X), rnd=torch.from_numpy(r)) for s, X, r in frames]
+    plan = fm.Plan(ctx, [d.descriptor() for d in devs], prec=fm.FM_FP16)
+    plan.run()
+    torch.cuda.synchronize()
+    plan.close()
+    ref = [d.results() for d in devs]
+    table = autotune.tune(ctx, devs, fm.FM_FP16, reps=2, log=say)
+    for knob, per in table.items():
+        for bucket, ch in per.items():
+            assert ch.value in autotune.choices(knob, bucket)
+            assert ch.value == min(ch.ms, key=lambda v: (ch.ms[v], v))
+            assert ctx.get_knob(knob, bucket) == ch.value
+    path = str(tmp_path / "tune.json")
+    key = autotune.cache_key(torch.cuda.get_device_name(0), autotune.library_id(), fm.FM_FP16)
+    autotune.save(path, key, table)
+    c2 = fm.Context(0, 1 << 20)
+    autotune.apply(c2, autotune.load(path, key))
+    for knob, per in table.items():
+        for bucket, ch in per.items():
+            assert c2.get_knob(knob, bucket) == ch.value
+    c2.close()
+    _same(ref, _run(ctx, frames, fm.FM_FP16, use_graph=True))
+
+
+@pytest.fixture(scope="module")
+def uneven_workload():
+    """Four frames of the uneven workload and their oracle results."""
+    shapes = fmsynth.uneven_batch(4, seed=73)
+    th0, dth, L = fmsynth.grid(18001)
+    frames, refs = [], []
+    for s in shapes:
+        fr = fmsynth.make_frame(s["M"], s["T"], s["K"], s["snr_db"], s["seed"],
+                                angle_range=(-75.0, 75.0), min_sep=1.0)
+        Om = fmsynth.make_omega(s["M"], s["l"], s["seed"])
+        spec = FrameSpec(M=s["M"], T=s["T"], K=s["K"], n=s["l"], q=s["q"], L=L, theta0_deg=th0,
+                         dtheta_deg=dth)
+        frames.append((spec, fr.X, Om))
+        refs.append(oracle.run_frame(fr.X, spec.K, "project", th0, dth, L, Omega=Om, q=spec.q,
+                                     threads=oracle.default_threads()))
+    return frames, refs
+
+
+@pytest.mark.parametrize("prec,bar", [(fm.FM_FP32, 1e-3), (fm.FM_FP16, 1e-2)])
+def test_uneven_workload_frames_match_oracle(ctx, uneven_workload, prec, bar):
+    frames, refs = uneven_workload
+    got = _run(ctx, frames, prec, use_graph=True)
+    for (spec, _X, _Om), g, ref in zip(frames, got, refs):
+        err = float(np.max(np.abs(10 * np.log10(g["P"].astype(np.float64) / ref["P"]))))
+        say(f"  M={spec.M} T={spec.T} K={spec.K}: max |dP| = {err:.3g} dB")
+        assert g["status"] == 0
+        assert err <= bar
+        assert g["n_found"] == len(ref["peak_idx"])
+        for pk in ref["peak_idx"]:
+            assert np.min(np.abs(g["peak_idx"] - pk)) <= 1
