@@ -48,11 +48,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def pmc_traffic(n_frames):
-    """HBM bytes per covariance launch from the committed rocprofv3 counter
-    summary, if it was taken on the current covariance source; else None."""
-    path = os.path.join(ROOT, "profiles", "covariance_m1024_t2048_pmc.md")
-    src = os.path.join(ROOT, "paper_1911_07434_amd", "csrc", "fm_cov.hip")
+def pmc_traffic(n_frames, prec="fp32"):
+    """HBM bytes per covariance launch of `n_frames` frames from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
+    counters on a device copy of known size), if it was taken on the current
+    covariance source; else None."""
+    name = "covariance_fp32" if prec == "fp32" else f"covariance_{prec}"
+    path = os.path.join(ROOT, "profiles", f"{name}_m1024_t2048_pmc.md")
+    src = os.path.join(ROOT, "paper_1911_07434_amd", "csrc",
+                       "fm_cov.hip" if prec == "fp32" else "fm_cov16.hip")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -226,7 +230,11 @@ def main():
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
-                    help="time only the main step (for profiler runs)")
+                    help="time only the main step (for profiler runs); same as --legs ''")
+    ap.add_argument("--legs", default="compare,uneven,serve",
+                    help="extra legs after the main step: compare (mixed precision, Method 1, "
+                         "standard MUSIC, latency alone), uneven (512-frame uneven batch), "
+                         "serve (Poisson serving trace)")
     ap.add_argument("--prec", choices=("fp32", "fp16", "bf16"), default="fp32",
                     help="covariance operand precision of the main timed step")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -238,6 +246,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
+    legs = set() if args.no_extra else {x for x in args.legs.split(",") if x}
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
               "multi-GPU form in this build", file=sys.stderr)
@@ -330,7 +339,7 @@ def main():
 
     cov_ms = stage_ms["covariance"]
     achieved = B * cov_flops(M, T) / (cov_ms * 1e-3) / 1e12
-    traffic = pmc_traffic(B) if args.prec == "fp32" else None
+    traffic = pmc_traffic(B, args.prec)
     peak = PEAK_FP32_MFMA_TFLOPS if args.prec == "fp32" else PEAK_F16_MFMA_TFLOPS
     kname = "cov_fp32_kernel" if args.prec == "fp32" else "cov16_kernel"
     roofline = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 2),
@@ -358,7 +367,7 @@ def main():
         "roofline": roofline,
     }
 
-    if not args.no_extra:
+    if "compare" in legs:
         # ---- mixed precision: 16-bit covariance operands, same frames ------
         mixed = {}
         for pname, prec in (("fp16", fm.FM_FP16), ("bf16", fm.FM_BF16)):
@@ -456,12 +465,12 @@ def main():
                                          "p99": round(float(np.percentile(lat, 99)), 3)}
 
     # ---- uneven batch in one graph launch, built-in vs autotuned variants ---
-    if not args.no_extra and args.uneven_steps > 0:
+    if "uneven" in legs and args.uneven_steps > 0:
         out["uneven_batch"] = uneven_leg(fm, torch, stream, args.seed + 7, args.uneven_steps,
                                          args.tune_cache)
 
     # ---- serving: Poisson arrivals of mixed-shape frames ---------------------
-    if not args.no_extra and args.serve_seconds > 0:
+    if "serve" in legs and args.serve_seconds > 0:
         del frames2
         torch.cuda.empty_cache()
         out["serving"] = serve_legs(ctx, fm, torch, args.serve_seconds, args.seed)

@@ -38,12 +38,12 @@ bool knob_value_ok(int knob, int bucket, int v) {
   return v == 64 || v == 128 || (v == 256 && bucket < 4);
 }
 
+// built-in choices (measured on an MI355X at the 1024-channel shapes): a
+// wider angle tile reuses each staged U_s operand for more angles until
+// register pressure from the 2K stacked outputs takes over
 int knob_default(int knob, int bucket) {
-  switch (knob) {
-    case FM_KNOB_COV_SCHEDULE: return 0;
-    case FM_KNOB_SPEC_ANGLES: return 64;
-    default: return bucket < 2 ? 256 : (bucket < 6 ? 128 : 64);
-  }
+  if (knob == FM_KNOB_COV_SCHEDULE) return 0;
+  return bucket < 2 ? 256 : (bucket < 6 ? 128 : 64);
 }
 
 // bucket of a covariance frame: log2(M) - 7 clamped to [0, 5]

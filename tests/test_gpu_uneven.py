@@ -71,7 +71,8 @@ def _same(a, b):
 
 def test_knob_defaults_and_validation(ctx):
     assert ctx.get_knob(fm.FM_KNOB_COV_SCHEDULE, 0) == 0
-    assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 3) == 64
+    assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 3) == 128
+    assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 7) == 64
     assert ctx.get_knob(fm.FM_KNOB_SPEC16_ANGLES, 0) == 256
     assert ctx.get_knob(fm.FM_KNOB_COV_SCHEDULE, 6) == -1      # no such bucket
     assert ctx.get_knob(7, 0) == -1
@@ -83,6 +84,8 @@ def test_knob_defaults_and_validation(ctx):
         assert e.value.status == fm.FM_E_ARG
     ctx.set_knob(fm.FM_KNOB_SPEC_ANGLES, 3, 256)
     assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 3) == 256
+    ctx.set_knob(fm.FM_KNOB_SPEC_ANGLES, 3, 64)
+    assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 3) == 64
 
 
 @pytest.mark.parametrize("prec", [fm.FM_FP32, fm.FM_FP16])
