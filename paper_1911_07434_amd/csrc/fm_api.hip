@@ -216,25 +216,27 @@ int sketch_nb(int n) { return (2 * n + 31) / 32; }
 // single-frame stage-2 sequences (identical kernels to the batched plan)
 // ---------------------------------------------------------------------------
 hipError_t run_project_single(FrameDev &f, hipStream_t s, fm_prec prec) {
+  (void)prec;
   hipError_t e;
-  auto orth = [&]() -> hipError_t {
+  const int nb = sketch_nb(f.n);
+  const bool fused = fm::sketch_fuses_gram(nb);
+  // orth of the current Y; `after_sketch`: the Gram partials came with it
+  auto orth = [&](bool after_sketch) -> hipError_t {
     hipError_t r;
-    if ((r = fm::launch_gram(f, nullptr, nullptr, 0, fm::kGramSelf, s)) != hipSuccess) return r;
+    if (!(fused && after_sketch) &&
+        (r = fm::launch_gram(f, nullptr, nullptr, 0, fm::kGramSelf, s)) != hipSuccess)
+      return r;
     if ((r = fm::launch_small(f, nullptr, nullptr, 0, fm::kOrth, s)) != hipSuccess) return r;
     return fm::launch_apply(f, nullptr, nullptr, 0, fm::kApplyV, s);
   };
   if ((e = fm::launch_omega(f, nullptr, nullptr, 0, 0, s)) != hipSuccess) return e;
-  if (f.q == 0) {
-    if ((e = orth()) != hipSuccess) return e;
-    if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, sketch_nb(f.n), prec, s)) != hipSuccess) return e;
-  } else {
-    if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, sketch_nb(f.n), prec, s)) != hipSuccess) return e;
-    for (int i = 0; i < f.q; ++i) {
-      if ((e = orth()) != hipSuccess) return e;
-      if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, sketch_nb(f.n), prec, s)) != hipSuccess) return e;
-    }
+  if (f.q == 0 && (e = orth(false)) != hipSuccess) return e;
+  for (int r = 0; r <= f.q; ++r) {
+    if (r > 0 && (e = orth(true)) != hipSuccess) return e;
+    if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, nb, r, s)) != hipSuccess) return e;
   }
-  if ((e = fm::launch_gram(f, nullptr, nullptr, 0, fm::kGramFinal, s)) != hipSuccess) return e;
+  if (!fused && (e = fm::launch_gram(f, nullptr, nullptr, 0, fm::kGramFinal, s)) != hipSuccess)
+    return e;
   if ((e = fm::launch_small(f, nullptr, nullptr, 0, fm::kFinal, s)) != hipSuccess) return e;
   return fm::launch_apply(f, nullptr, nullptr, 0, fm::kApplyUs, s);
 }
@@ -468,7 +470,7 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kCov: return fm::launch_covariance(cls, fr, it, L.count, p->prec, s);
     case kOmega: return fm::launch_omega(cls, fr, it, L.count, 0, s);
     case kGather: return fm::launch_gather(cls, fr, it, L.count, s);
-    case kSketch: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, FM_FP32, s);
+    case kSketch: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, L.mode, s);
     case kGram: return fm::launch_gram(cls, fr, it, L.count, L.mode, s);
     case kSmall: return fm::launch_small(cls, fr, it, L.count, L.mode, s);
     case kApply: return fm::launch_apply(cls, fr, it, L.count, L.mode, s);
@@ -661,10 +663,15 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   add(p->sub, kGather, 0, 0, b0);
 
   const int classes[4] = {16, 32, fm::kSmallLdsN, fm::kMaxN};
-  auto orth_round = [&](auto pred) {
+  // a sketch of a column class that fuses the Gram step leaves its partials
+  auto fused = [&](int i) {
+    return frames[i].method == FM_METHOD_PROJECT && fm::sketch_fuses_gram(sketch_nb(frames[i].n));
+  };
+  // after_sketch: this orth follows a product (round >= 1)
+  auto orth_round = [&](auto pred, bool after_sketch) {
     size_t b = begin();
     for (int i : order)
-      if (pred(i))
+      if (pred(i) && !(after_sketch && fused(i)))
         for (int c = 0; c < rows(frames[i].M, fm::kGramRows); ++c) items.push_back({i, c, 0, 0});
     add(p->sub, kGram, fm::kGramSelf, 0, b);
     for (int cl : classes) {
@@ -679,14 +686,14 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
         for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
     add(p->sub, kApply, fm::kApplyV, 0, b);
   };
-  auto sketch_round = [&](auto pred) {
+  auto sketch_round = [&](auto pred, int round) {
     for (int nb = 1; nb <= 4; ++nb) {
       size_t b = begin();
       for (int i : order)
         if (pred(i) && sketch_nb(frames[i].n) == nb)
           for (int c = 0; c < rows(frames[i].M, fm::kSketchRows); ++c)
             items.push_back({i, c, 0, 0});
-      add(p->sub, kSketch, 0, nb, b);
+      add(p->sub, kSketch, round, nb, b);
     }
   };
   int qmax = 0;
@@ -694,16 +701,17 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     if (frames[i].method == FM_METHOD_PROJECT) qmax = std::max(qmax, frames[i].q);
   auto is_proj = [&](int i) { return frames[i].method == FM_METHOD_PROJECT; };
   // round 0: orth(Omega) for q = 0 frames, then the first product for all
-  orth_round([&](int i) { return is_proj(i) && frames[i].q == 0; });
-  sketch_round(is_proj);
+  orth_round([&](int i) { return is_proj(i) && frames[i].q == 0; }, false);
+  sketch_round(is_proj, 0);
   for (int r = 1; r <= qmax; ++r) {
-    orth_round([&](int i) { return is_proj(i) && frames[i].q >= r; });
-    sketch_round([&](int i) { return is_proj(i) && frames[i].q >= r; });
+    orth_round([&](int i) { return is_proj(i) && frames[i].q >= r; }, true);
+    sketch_round([&](int i) { return is_proj(i) && frames[i].q >= r; }, r);
   }
-  // final: core and Gram, eigen-solves, U_s
+  // final: core and Gram (unless the last product formed them), eigen-solves, U_s
   b0 = begin();
   for (int i : order)
-    for (int c = 0; c < rows(frames[i].M, fm::kGramRows); ++c) items.push_back({i, c, 0, 0});
+    if (!fused(i))
+      for (int c = 0; c < rows(frames[i].M, fm::kGramRows); ++c) items.push_back({i, c, 0, 0});
   add(p->sub, kGram, fm::kGramFinal, 0, b0);
   for (int cl : classes) {
     b0 = begin();

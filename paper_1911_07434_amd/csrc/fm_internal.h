@@ -91,9 +91,15 @@ hipError_t launch_covariance16(const FrameDev &single, const FrameDev *frames,
                                const Item *items, int n_items, fm_prec prec, hipStream_t s);
 hipError_t launch_omega(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, int to_y, hipStream_t s);
-// nb = ceil(2n / 32): MFMA column blocks of the sketch (one launch per class)
+// nb = ceil(2n / 32): MFMA column blocks of the sketch (one launch per class).
+// round >= 0: index of this product among the frame's q + 1; for nb <= 2 the
+// launch also writes the Gram partials of the step that follows (kGramSelf
+// if round < q, else kGramFinal), which then needs no gram launch.  round < 0:
+// sketch only.
 hipError_t launch_sketch(const FrameDev &single, const FrameDev *frames, const Item *items,
-                         int n_items, int nb, fm_prec prec, hipStream_t s);
+                         int n_items, int nb, int round, hipStream_t s);
+// whether a sketch of this column class forms its Gram partials itself
+inline bool sketch_fuses_gram(int nb) { return nb <= 2; }
 hipError_t launch_gather(const FrameDev &single, const FrameDev *frames, const Item *items,
                          int n_items, hipStream_t s);
 hipError_t launch_gram(const FrameDev &single, const FrameDev *frames, const Item *items,

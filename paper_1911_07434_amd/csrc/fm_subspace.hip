@@ -96,12 +96,34 @@ __global__ __launch_bounds__(256) void omega_kernel(FrameDev single, const Frame
 // the first half with column 16+s of the second.
 // ---------------------------------------------------------------------------
 constexpr int kSkChunkMax = 32;
+static_assert(kSketchRows == kGramRows, "a sketch workgroup covers one Gram chunk");
+static_assert(kSkChunkMax * kMaxL * 2 >= kSketchRows * 32, "Y tile of n <= 32 fits the V buffers");
 typedef FM_GLOBAL const float2 gfloat2;
+
+// out[a][b] = sum over rows m of conj(A[m][a]) B[m][b] in FP64 (the products
+// of FP32 inputs are exact), rows in order: the Gram partial of one chunk,
+// one entry per thread at a time.  Same per-entry order as gram_block.
+__device__ __forceinline__ void gram_rows(const float2 *A, const float2 *B, double2 *out, int n,
+                                          int rows) {
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int a = e / n, b = e % n;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int m = 0; m < rows; ++m) {
+      const float2 av = A[(size_t)m * n + a], bv = B[(size_t)m * n + b];
+      const double ar = av.x, ai = av.y, br = bv.x, bi = bv.y;
+      acc.x = fma(ar, br, acc.x);
+      acc.x = fma(ai, bi, acc.x);
+      acc.y = fma(ar, bi, acc.y);
+      acc.y = fma(-ai, br, acc.y);
+    }
+    out[e] = acc;
+  }
+}
 
 // SK = elements of its row each lane holds per chunk (chunk = 2 SK columns);
 // wide column classes use SK = 8 to stay within the register file
 template <int NB, int SK>
-__device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0,
+__device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk, int gmode,
                                             float2 (*vbuf)[kSkChunkMax * kMaxL]) {
   constexpr int kSkChunk = 2 * SK;
   const int tid = threadIdx.x;
@@ -208,21 +230,50 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0,
       if (i < M) Yf[((size_t)i * n + col[b]) * 2 + part[b]] = acc[b][v];
     }
   }
+  if constexpr (NB <= 2) {
+    // Gram partials of this workgroup's 128 rows of Y (the chunk the Gram
+    // step sums over), from the FP32 values just stored, staged in LDS
+    if (gmode < 0) return;
+    __syncthreads();  // every wave is done with the V buffers
+    float *yt = reinterpret_cast<float *>(&vbuf[0][0]);  // [128][n] complex
+    const int il0 = (tid >> 6) * 32;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (!okc[b]) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int il = il0 + (v >> 2) * 8 + h * 4 + (v & 3);
+        yt[(il * n + col[b]) * 2 + part[b]] = acc[b][v];
+      }
+    }
+    __syncthreads();
+    const int m0 = chunk * kGramRows;
+    const int rows = min(M, m0 + kGramRows) - m0;
+    const float2 *Yt = reinterpret_cast<const float2 *>(yt);
+    gram_rows(Yt, Yt, f.part + (size_t)(chunk * 2 + (gmode == kGramSelf ? 0 : 1)) * n * n, n,
+              rows);
+    if (gmode == kGramFinal)
+      gram_rows(f.V + (size_t)m0 * n, Yt, f.part + (size_t)(chunk * 2) * n * n, n, rows);
+  }
 }
 
 // one instantiation per NB = ceil(2n / 32); a launch only holds frames of one
 // class (the plan groups them), so no kernel carries the registers of a
 // wider class
+// `round` is the index of this product among the frame's q + 1: for column
+// classes NB <= 2 the Gram partials that follow it (orth of the next round,
+// or the final core and Gram after the last product) are formed here.
 template <int NB, bool kBatched>
 __global__ __launch_bounds__(256) void sketch_kernel(FrameDev single, const FrameDev *frames,
-                                                     const Item *items) {
+                                                     const Item *items, int round) {
   __shared__ float2 vbuf[2][kSkChunkMax * kMaxL];
   int blk, unused;
   const FrameDev &f = frame_of<kBatched>(single, frames, items, blk, unused);
   // every wave takes part in the V staging and the barriers; waves whose
   // rows start past M clamp to row M-1 and store nothing
   const int i0 = blk * kSketchRows + (threadIdx.x >> 6) * 32;
-  sketch_rows<NB, (NB <= 2 ? 16 : 8)>(f, i0, vbuf);
+  const int gmode = round < 0 ? -1 : (round < f.q ? kGramSelf : kGramFinal);
+  sketch_rows<NB, (NB <= 2 ? 16 : 8)>(f, i0, blk, gmode, vbuf);
 }
 
 // ---------------------------------------------------------------------------
@@ -707,12 +758,12 @@ hipError_t launch_omega(const FrameDev &single, const FrameDev *frames, const It
 }
 
 hipError_t launch_sketch(const FrameDev &single, const FrameDev *frames, const Item *items,
-                         int n_items, int nb, fm_prec prec, hipStream_t s) {
-  (void)prec;
+                         int n_items, int nb, int round, hipStream_t s) {
   const dim3 g(items ? n_items : (single.M + kSketchRows - 1) / kSketchRows), b(256);
-#define FM_SK(NB)                                                                            \
-  if (items) hipLaunchKernelGGL((sketch_kernel<NB, true>), g, b, 0, s, single, frames, items); \
-  else hipLaunchKernelGGL((sketch_kernel<NB, false>), g, b, 0, s, single, frames, items);
+  const int rd = nb <= 2 ? round : -1;
+#define FM_SK(NB)                                                                                 \
+  if (items) hipLaunchKernelGGL((sketch_kernel<NB, true>), g, b, 0, s, single, frames, items, rd); \
+  else hipLaunchKernelGGL((sketch_kernel<NB, false>), g, b, 0, s, single, frames, items, rd);
   switch (nb) {
     case 1: FM_SK(1); break;
     case 2: FM_SK(2); break;
