@@ -46,10 +46,14 @@ __device__ __forceinline__ const FrameDev &spec_frame(const FrameDev &single,
   }
 }
 
-// FP64 denominator of one angle, computed by the whole wave: each lane
+// FP64 denominators of the four angles Fw (one per wave; a wave with no
+// angle passes active = false but still stages and synchronises).  Each lane
 // walks every 64th channel with an FP64 phasor recurrence (64 steps at most
-// per exact start, error ~1e-14), K accumulated 16 at a time.
-__device__ double den_fp64(const FrameDev &f, unsigned long long F, int lane) {
+// per exact start, error ~1e-14), K accumulated 16 at a time.  U_s is staged
+// through LDS 16 sources x 64 channels at a time and shared by the four
+// waves, so the workgroup reads it once per four angles.
+__device__ double den_fp64_x4(const FrameDev &f, unsigned long long F, bool active, int lane,
+                              double2 (*us)[64]) {
   const int M = f.M, K = f.K;
   double proj = 0.0;
   const double2 w = phasor64(64, F);
@@ -59,14 +63,23 @@ __device__ double den_fp64(const FrameDev &f, unsigned long long F, int lane) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[k] = make_double2(0.0, 0.0);
     double2 a = phasor64((unsigned long long)lane, F);
-    for (int m = lane; m < M; m += 64) {
+    for (int mc = 0; mc < M; mc += 64) {
+      __syncthreads();  // the previous chunk has been read by every wave
+      for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) {
+        const int k = e >> 6, m = mc + (e & 63);
+        us[k][e & 63] = (k < kn && m < M) ? f.Us[(size_t)(k0 + k) * M + m]
+                                          : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+      if (active && mc + lane < M) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        if (k < kn) {
-          const double2 u = f.Us[(size_t)(k0 + k) * M + m];
-          // conj(u) * a
-          acc[k].x = fma(u.x, a.x, fma(u.y, a.y, acc[k].x));
-          acc[k].y = fma(u.x, a.y, fma(-u.y, a.x, acc[k].y));
+        for (int k = 0; k < 16; ++k) {
+          if (k < kn) {
+            const double2 u = us[k][lane];
+            // conj(u) * a
+            acc[k].x = fma(u.x, a.x, fma(u.y, a.y, acc[k].x));
+            acc[k].y = fma(u.x, a.y, fma(-u.y, a.x, acc[k].y));
+          }
         }
       }
       a = make_double2(fma(a.x, w.x, -(a.y * w.y)), fma(a.x, w.y, a.y * w.x));
@@ -216,17 +229,21 @@ __global__ __launch_bounds__(256) void spectrum_kernel(FrameDev single, const Fr
 template <bool kBatched>
 __global__ __launch_bounds__(256) void refine_kernel(FrameDev single, const FrameDev *frames,
                                                      const Item *items) {
+  __shared__ double2 us[16][64];
   int part;
   const FrameDev &f = spec_frame<kBatched>(single, frames, items, part);
   const int lane = threadIdx.x & 63;
   const int gw = part * 4 + (threadIdx.x >> 6);
   const int cnt = f.rlist[0];
   const double floor64 = (double)f.M * 1.1102230246251565e-16;  // M * 2^-53
-  for (int e = gw; e < cnt; e += kRefineGroups * 4) {
-    const int gl = f.rlist[1 + e];
+  // the four waves take four consecutive list entries per step (uniform loop)
+  for (int e0 = part * 4; e0 < cnt; e0 += kRefineGroups * 4) {
+    const int e = e0 + (gw - part * 4);
+    const bool active = e < cnt;
+    const int gl = active ? f.rlist[1 + e] : 0;
     const unsigned long long F = turn_freq(f.theta0, f.dtheta, gl);
-    const double d = den_fp64(f, F, lane);
-    if (lane == 0) f.P[gl] = (float)(1.0 / fmax(d, floor64));
+    const double d = den_fp64_x4(f, F, active, lane, us);
+    if (active && lane == 0) f.P[gl] = (float)(1.0 / fmax(d, floor64));
   }
 }
 

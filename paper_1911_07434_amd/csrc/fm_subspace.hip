@@ -713,22 +713,38 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
 // apply: V = Y T (ORTH, complex64 [M][n]) or U_s = C T_f (FINAL, complex128
 // [K][M] plus the FP32 copy Uf [M][K] used by the spectrum pass)
 // ---------------------------------------------------------------------------
+// T (n x ncol complex128) and the chunk's rows of Y are staged in LDS when
+// T fits (n * ncol <= kApplyTMax); Y is staged column-major so that the
+// lanes of a wave (consecutive rows) read consecutive words.
+constexpr int kApplyTMax = 1024;
 template <bool kBatched>
 __global__ __launch_bounds__(256) void apply_kernel(FrameDev single, const FrameDev *frames,
                                                     const Item *items, int mode) {
+  __shared__ double2 ts[kApplyTMax];
+  __shared__ float2 ys[kApplyRows * kMaxL];
   int chunk, unused;
   const FrameDev &f = frame_of<kBatched>(single, frames, items, chunk, unused);
   const int n = f.n, M = f.M;
   const int m0 = chunk * kApplyRows;
   const int rows = min(M, m0 + kApplyRows) - m0;
   const double2 *Tm = slot(f, kSlotT);
+  const float2 *Y = f.Y;
   const int ncol = mode == kApplyV ? n : f.K;
+  const bool staged = n * ncol <= kApplyTMax && n <= kMaxL;
+  if (staged) {
+    for (int e = threadIdx.x; e < n * ncol; e += blockDim.x) ts[e] = Tm[e];
+    for (int e = threadIdx.x; e < rows * n; e += blockDim.x) {
+      const int m = e / n, j = e % n;
+      ys[j * kApplyRows + m] = Y[(size_t)(m0 + m) * n + j];
+    }
+    __syncthreads();
+  }
   for (int e = threadIdx.x; e < rows * ncol; e += blockDim.x) {
-    const int c = e / rows, m = m0 + e % rows;
+    const int c = e / rows, ml = e % rows, m = m0 + ml;
     double2 acc = make_double2(0.0, 0.0);
     for (int j = 0; j < n; ++j) {
-      const float2 y = f.Y[(size_t)m * n + j];
-      const double2 t = Tm[(size_t)j * ncol + c];
+      const float2 y = staged ? ys[j * kApplyRows + ml] : Y[(size_t)m * n + j];
+      const double2 t = staged ? ts[j * ncol + c] : Tm[(size_t)j * ncol + c];
       acc.x = fma((double)y.x, t.x, acc.x);
       acc.x = fma(-(double)y.y, t.y, acc.x);
       acc.y = fma((double)y.x, t.y, acc.y);
