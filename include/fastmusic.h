@@ -70,10 +70,13 @@ typedef enum {
  *     halves and accumulates hi*hi + hi*lo + lo*hi (~22-bit products).
  *     fm_pseudospectrum rejects FM_BF16 (FM_E_UNSUPPORTED); a plan at either
  *     16-bit precision runs the FP16 split spectrum.
- *   sketch products (fm_subspace_*, stage 2 of a plan): FP32 in every mode
- *     (fm_subspace_project rejects 16-bit precisions with FM_E_UNSUPPORTED): a
- *     plain 16-bit rounding of R perturbs the peak-region denominators by more
- *     than 1e-2 dB.
+ *   sketch products Y = R V (fm_subspace_project, stage 2 of a plan):
+ *     FM_FP32 uses FP32 products; FM_FP16 and FM_BF16 split R and V into
+ *     FP16 hi + lo halves (power-of-two scaled) and accumulate hi*hi + hi*lo
+ *     + lo*hi, for sketch widths l <= 32 (wider sketches use FP32 products).
+ *     A plain 16-bit rounding of R would move the peak-region denominators
+ *     by more than 1e-2 dB, so no precision drops the lo halves.  Method 1
+ *     (fm_subspace_sample) has no such product.
  * The small dense steps (orthonormalisation, eigen-solves, peak-region
  * denominators) are FP64 in every mode. */
 typedef enum {
@@ -237,7 +240,8 @@ typedef struct {
  * frame, builds the per-stage work lists (longest-first), uploads them and
  * allocates the plan's workspace.  Synchronises the device once.  Each
  * frame is computed exactly as the single-frame entry points compute it:
- * fm_covariance at the plan's precision `prec`, fm_subspace_* at FM_FP32,
+ * fm_covariance and fm_subspace_project at the plan's precision `prec`,
+ * fm_subspace_sample at FM_FP32,
  * fm_pseudospectrum at FM_FP32 for an FP32 plan and at FM_FP16 for a 16-bit
  * plan. */
 fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,

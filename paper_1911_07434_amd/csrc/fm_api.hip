@@ -83,8 +83,8 @@ struct fm_plan {
 
 namespace {
 
-enum Kind { kCov, kOmega, kGather, kSketch, kGram, kSmall, kApply, kSpecPrep, kSpec, kSplit,
-             kSpec16, kRefine,
+enum Kind { kCov, kOmega, kGather, kSketch, kSketch16, kGram, kSmall, kApply, kSpecPrep, kSpec,
+             kSplit, kSpec16, kRefine,
             kPeaks };
 
 fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
@@ -216,9 +216,13 @@ int sketch_nb(int n) { return (2 * n + 31) / 32; }
 // single-frame stage-2 sequences (identical kernels to the batched plan)
 // ---------------------------------------------------------------------------
 hipError_t run_project_single(FrameDev &f, hipStream_t s, fm_prec prec) {
-  (void)prec;
   hipError_t e;
   const int nb = sketch_nb(f.n);
+  const bool s16 = prec != FM_FP32 && fm::sketch16_ok(nb);
+  auto sketch = [&](int r) {
+    return s16 ? fm::launch_sketch16(f, nullptr, nullptr, 0, nb, r, s)
+               : fm::launch_sketch(f, nullptr, nullptr, 0, nb, r, s);
+  };
   const bool fused = fm::sketch_fuses_gram(nb);
   // orth of the current Y; `after_sketch`: the Gram partials came with it
   auto orth = [&](bool after_sketch) -> hipError_t {
@@ -233,7 +237,7 @@ hipError_t run_project_single(FrameDev &f, hipStream_t s, fm_prec prec) {
   if (f.q == 0 && (e = orth(false)) != hipSuccess) return e;
   for (int r = 0; r <= f.q; ++r) {
     if (r > 0 && (e = orth(true)) != hipSuccess) return e;
-    if ((e = fm::launch_sketch(f, nullptr, nullptr, 0, nb, r, s)) != hipSuccess) return e;
+    if ((e = sketch(r)) != hipSuccess) return e;
   }
   if (!fused && (e = fm::launch_gram(f, nullptr, nullptr, 0, fm::kGramFinal, s)) != hipSuccess)
     return e;
@@ -356,7 +360,7 @@ static fm_status subspace_single(fm_ctx *ctx, void *stream, const void *R, int M
   fm_status st = check_sub(ctx, R, M, ldr, method, n, q, K, rcond, rnd, Us, sigma, status);
   if (st != FM_OK) return st;
   if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "subspace: bad precision %d", (int)prec);
-  if (prec != FM_FP32) return fail(ctx, FM_E_UNSUPPORTED, "subspace: only FM_FP32 in this build");
+
   const WsLayout w = ws_layout(M, n, K, 0);
   if (w.total > ctx->arena_bytes)
     return fail(ctx, FM_E_WORKSPACE, "subspace: needs %zu arena bytes, have %zu", w.total,
@@ -471,6 +475,7 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kOmega: return fm::launch_omega(cls, fr, it, L.count, 0, s);
     case kGather: return fm::launch_gather(cls, fr, it, L.count, s);
     case kSketch: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, L.mode, s);
+    case kSketch16: return fm::launch_sketch16(cls, fr, it, L.count, L.n_class, L.mode, s);
     case kGram: return fm::launch_gram(cls, fr, it, L.count, L.mode, s);
     case kSmall: return fm::launch_small(cls, fr, it, L.count, L.mode, s);
     case kApply: return fm::launch_apply(cls, fr, it, L.count, L.mode, s);
@@ -693,7 +698,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
         if (pred(i) && sketch_nb(frames[i].n) == nb)
           for (int c = 0; c < rows(frames[i].M, fm::kSketchRows); ++c)
             items.push_back({i, c, 0, 0});
-      add(p->sub, kSketch, round, nb, b);
+      add(p->sub, (prec != FM_FP32 && fm::sketch16_ok(nb)) ? kSketch16 : kSketch, round, nb, b);
     }
   };
   int qmax = 0;

@@ -100,6 +100,11 @@ hipError_t launch_sketch(const FrameDev &single, const FrameDev *frames, const I
                          int n_items, int nb, int round, hipStream_t s);
 // whether a sketch of this column class forms its Gram partials itself
 inline bool sketch_fuses_gram(int nb) { return nb <= 2; }
+// compensated FP16 sketch (16-bit plans and calls), nb <= 2 only; forms the
+// Gram partials like launch_sketch
+hipError_t launch_sketch16(const FrameDev &single, const FrameDev *frames, const Item *items,
+                           int n_items, int nb, int round, hipStream_t s);
+inline bool sketch16_ok(int nb) { return nb <= 2; }
 hipError_t launch_gather(const FrameDev &single, const FrameDev *frames, const Item *items,
                          int n_items, hipStream_t s);
 hipError_t launch_gram(const FrameDev &single, const FrameDev *frames, const Item *items,

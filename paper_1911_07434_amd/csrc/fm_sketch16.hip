@@ -1,0 +1,253 @@
+// fm_sketch16.hip -- Method 2 products Y = R V (Alg. 2, eq. (11)) on 16-bit
+// matrix cores with compensated operands, for the mixed-precision path.
+//
+// Complex product as one real contraction with the (re, im) pairs of each
+// channel m interleaved on the MFMA K index: row i of A is R[i][.] as stored
+// (Rr_m, Ri_m), and column c of B is (Vr_m, -Vi_m) for Re Y[i][c] and
+// (Vi_m, Vr_m) for Im Y[i][c]:
+//   Re Y = sum_m Rr Vr - Ri Vi,   Im Y = sum_m Rr Vi + Ri Vr.
+// Both operands are split into FP16 hi + lo halves and hi.hi + hi.lo + lo.hi
+// accumulate in FP32 (~22-bit products) on v_mfma_f32_32x32x16_f16.  R is
+// read straight from HBM (the kernel's bound) and split in registers; V is
+// split once per workgroup and chunk into LDS.  Power-of-two scales keep
+// both halves in FP16's normal range: R by 2^(8 - ceil(log2 max_i R_ii))
+// (every |R_ij| <= max_i R_ii), V by 2^round(log2 sqrt(M)) when V is an
+// orthonormal basis; Y is unscaled exactly before it is stored.
+//
+// Layout of a workgroup: four waves x 32 rows of R, 2n <= 64 real output
+// columns in NB blocks of 32 (Re Y_c in column c, Im Y_c in column n + c, as
+// the FP32 sketch).  Channels go in chunks of 32: per chunk a lane loads 4 x
+// 4 complex values of its row (one MFMA K-slice each), prefetched a chunk
+// ahead.  The epilogue forms the Gram partials of the workgroup's 128 rows,
+// exactly as the FP32 sketch does.
+#include "fm_internal.h"
+#include "fm_gram.h"
+
+namespace fm {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef FM_GLOBAL const f32x4 gf32x4;
+typedef FM_GLOBAL const f32x2 gf32x2;
+
+constexpr int kCh = 32;              // channels per chunk
+constexpr int kBRow = 2 * kCh + 8;   // halves per B column in LDS (16 bytes of padding)
+
+template <bool kBatched>
+__device__ __forceinline__ const FrameDev &frame16(const FrameDev &single, const FrameDev *frames,
+                                                   const Item *items, int &blk) {
+  if constexpr (kBatched) {
+    const Item &it = items[blockIdx.x];
+    blk = it.a;
+    return frames[it.frame];
+  } else {
+    blk = blockIdx.x;
+    return single;
+  }
+}
+
+__device__ __forceinline__ void split8(const f32x4 &x0, const f32x4 &x1, float s, h8 &hi,
+                                       h8 &lo) {
+  const float v[8] = {x0.x * s, x0.y * s, x0.z * s, x0.w * s,
+                      x1.x * s, x1.y * s, x1.z * s, x1.w * s};
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    hi[j] = (_Float16)v[j];
+    lo[j] = (_Float16)(v[j] - (float)hi[j]);
+  }
+}
+
+template <int NB, bool kBatched>
+__global__ __launch_bounds__(256) void sketch16_kernel(FrameDev single, const FrameDev *frames,
+                                                       const Item *items, int round) {
+  constexpr int kPlane = 32 * NB * kBRow;  // halves in one plane (hi or lo) of one buffer
+  __shared__ __attribute__((aligned(16))) _Float16 bsm[2 * 2 * kPlane];
+  __shared__ float red[4];
+  int blk;
+  const FrameDev &f = frame16<kBatched>(single, frames, items, blk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 31, h = lane >> 5;
+  const int M = f.M, n = f.n;
+  const long long ldr = f.ldr;
+  const float2 *R = f.R;
+  const float2 *V = f.V;
+  const int i0 = blk * kSketchRows + wave * 32;
+
+  // scales: R from its largest diagonal entry, V from its kind
+  {
+    float mx = 0.f;
+    for (int i = tid; i < M; i += blockDim.x) mx = fmaxf(mx, R[(size_t)i * ldr + i].x);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (lane == 0) red[wave] = mx;
+  }
+  __syncthreads();
+  const float rmax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  const float sR = (rmax > 0.f && rmax < 3.0e38f) ? exp2f(8.f - ceilf(log2f(rmax))) : 1.f;
+  const bool orth_v = round > 0 || f.q == 0;   // round 0 with q > 0 multiplies Omega
+  const float sV = orth_v ? exp2f(rintf(0.5f * log2f((float)M))) : 1.f;
+
+  // zero the B columns past 2n once (both buffers, both planes)
+  for (int e = tid; e < 4 * kPlane; e += blockDim.x) {
+    const int col = (e % kPlane) / kBRow;
+    if (col >= 2 * n) bsm[e] = (_Float16)0.f;
+  }
+
+  // B staging: the V chunk (kCh x n complex) as split columns
+  auto stage_b = [&](int c, int buf) {
+    _Float16 *bh = bsm + buf * 2 * kPlane, *bl = bh + kPlane;
+    for (int e = tid; e < kCh * n; e += blockDim.x) {
+      const int ml = e / n, cc = e % n, m = c * kCh + ml;
+      float2 v = make_float2(0.f, 0.f);
+      if (m < M) v = V[(size_t)m * n + cc];
+      const float vr = v.x * sV, vi = v.y * sV;
+      const float q[4] = {vr, -vi, vi, vr};   // Re column: (vr, -vi); Im column: (vi, vr)
+      _Float16 qh[4], ql[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        qh[j] = (_Float16)q[j];
+        ql[j] = (_Float16)(q[j] - (float)qh[j]);
+      }
+      const int ore = cc * kBRow + 2 * ml, oim = (n + cc) * kBRow + 2 * ml;
+      bh[ore] = qh[0];
+      bh[ore + 1] = qh[1];
+      bh[oim] = qh[2];
+      bh[oim + 1] = qh[3];
+      bl[ore] = ql[0];
+      bl[ore + 1] = ql[1];
+      bl[oim] = ql[2];
+      bl[oim + 1] = ql[3];
+    }
+  };
+
+  // A prefetch: for K-slice ks (8 channels) the lane holds channels
+  // 8 ks + 4 h .. + 3 of its row = two float4
+  const int row = min(i0 + r, M - 1);
+  const float *Rrow = reinterpret_cast<const float *>(R + (size_t)row * ldr);
+  auto load_r = [&](f32x4 (&a)[8], int c) {
+    const int mb = c * kCh;
+    if (mb + kCh <= M) {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          a[2 * ks + q] = *(gf32x4 *)(Rrow + 2 * (mb + 8 * ks + 4 * h + 2 * q));
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int m = mb + 8 * ks + 4 * h + 2 * q;
+          f32x4 x = f32x4{0.f, 0.f, 0.f, 0.f};
+          if (m < M) {
+            const f32x2 y = *(gf32x2 *)(Rrow + 2 * m);
+            x.x = y.x;
+            x.y = y.y;
+          }
+          if (m + 1 < M) {
+            const f32x2 y = *(gf32x2 *)(Rrow + 2 * (m + 1));
+            x.z = y.x;
+            x.w = y.y;
+          }
+          a[2 * ks + q] = x;
+        }
+    }
+  };
+
+  floatx16 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
+
+  auto compute = [&](const f32x4 (&a)[8], int buf) {
+    const _Float16 *bh = bsm + buf * 2 * kPlane, *bl = bh + kPlane;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      h8 ahi, alo;
+      split8(a[2 * ks], a[2 * ks + 1], sR, ahi, alo);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int o = (32 * b + r) * kBRow + 16 * ks + 8 * h;
+        const h8 bhi = *(const h8 *)(bh + o);
+        const h8 blo = *(const h8 *)(bl + o);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, bhi, acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, blo, acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, bhi, acc[b], 0, 0, 0);
+      }
+    }
+  };
+
+  const int nchunk = (M + kCh - 1) / kCh;
+  f32x4 a0[8], a1[8];
+  __syncthreads();  // zero columns written before any staging
+  stage_b(0, 0);
+  load_r(a0, 0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; c += 2) {
+    const bool has1 = c + 1 < nchunk;
+    if (has1) {
+      load_r(a1, c + 1);
+      stage_b(c + 1, 1);
+    }
+    compute(a0, 0);
+    __syncthreads();
+    if (!has1) break;
+    const bool has2 = c + 2 < nchunk;
+    if (has2) {
+      load_r(a0, c + 2);
+      stage_b(c + 2, 0);
+    }
+    compute(a1, 1);
+    __syncthreads();
+  }
+
+  // store Y (unscaled), Re Y_c from column c, Im Y_c from column n + c
+  const float inv = 1.f / (sR * sV);
+  float *Yf = reinterpret_cast<float *>(f.Y);
+  float *yt = reinterpret_cast<float *>(bsm);   // [128][n] complex tile for the Gram step
+  const int gmode = round < 0 ? -1 : (round < f.q ? kGramSelf : kGramFinal);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int nn = 32 * b + r;
+    if (nn >= 2 * n) continue;
+    const int part = nn < n ? 0 : 1, col = nn < n ? nn : nn - n;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int il = wave * 32 + (v >> 2) * 8 + h * 4 + (v & 3);
+      const float y = acc[b][v] * inv;
+      if (blk * kSketchRows + il < M) Yf[((size_t)(blk * kSketchRows + il) * n + col) * 2 + part] = y;
+      if (gmode >= 0) yt[(il * n + col) * 2 + part] = y;
+    }
+  }
+  if (gmode < 0) return;
+  __syncthreads();
+  const int m0 = blk * kGramRows;
+  const int rows = min(M, m0 + kGramRows) - m0;
+  const float2 *Yt = reinterpret_cast<const float2 *>(yt);
+  gram_rows(Yt, Yt, f.part + (size_t)(blk * 2 + (gmode == kGramSelf ? 0 : 1)) * n * n, n, rows);
+  if (gmode == kGramFinal)
+    gram_rows(f.V + (size_t)m0 * n, Yt, f.part + (size_t)(blk * 2) * n * n, n, rows);
+}
+
+template <int NB>
+hipError_t launch16(const FrameDev &single, const FrameDev *frames, const Item *items,
+                    int n_items, int round, hipStream_t s) {
+  const dim3 g(items ? n_items : (single.M + kSketchRows - 1) / kSketchRows), b(256);
+  if (items) hipLaunchKernelGGL((sketch16_kernel<NB, true>), g, b, 0, s, single, frames, items, round);
+  else hipLaunchKernelGGL((sketch16_kernel<NB, false>), g, b, 0, s, single, frames, items, round);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sketch16(const FrameDev &single, const FrameDev *frames, const Item *items,
+                           int n_items, int nb, int round, hipStream_t s) {
+  return nb <= 1 ? launch16<1>(single, frames, items, n_items, round, s)
+                 : launch16<2>(single, frames, items, n_items, round, s);
+}
+
+}  // namespace fm

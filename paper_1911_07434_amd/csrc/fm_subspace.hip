@@ -23,6 +23,7 @@
 //           products, in FP64 (LDS-resident up to n = 64)
 //   apply   V = Y T (complex64) or U_s = C T_f (complex128 + FP32 copy)
 #include "fm_internal.h"
+#include "fm_gram.h"
 
 namespace fm {
 namespace {
@@ -99,26 +100,6 @@ constexpr int kSkChunkMax = 32;
 static_assert(kSketchRows == kGramRows, "a sketch workgroup covers one Gram chunk");
 static_assert(kSkChunkMax * kMaxL * 2 >= kSketchRows * 32, "Y tile of n <= 32 fits the V buffers");
 typedef FM_GLOBAL const float2 gfloat2;
-
-// out[a][b] = sum over rows m of conj(A[m][a]) B[m][b] in FP64 (the products
-// of FP32 inputs are exact), rows in order: the Gram partial of one chunk,
-// one entry per thread at a time.  Same per-entry order as gram_block.
-__device__ __forceinline__ void gram_rows(const float2 *A, const float2 *B, double2 *out, int n,
-                                          int rows) {
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int a = e / n, b = e % n;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int m = 0; m < rows; ++m) {
-      const float2 av = A[(size_t)m * n + a], bv = B[(size_t)m * n + b];
-      const double ar = av.x, ai = av.y, br = bv.x, bi = bv.y;
-      acc.x = fma(ar, br, acc.x);
-      acc.x = fma(ai, bi, acc.x);
-      acc.y = fma(ar, bi, acc.y);
-      acc.y = fma(-ai, br, acc.y);
-    }
-    out[e] = acc;
-  }
-}
 
 // SK = elements of its row each lane holds per chunk (chunk = 2 SK columns);
 // wide column classes use SK = 8 to stay within the register file

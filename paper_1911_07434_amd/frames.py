@@ -86,14 +86,14 @@ class DeviceFrame:
 
 def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
     """All four stages of one frame through the single-frame entry points, as
-    a plan at precision `prec` runs them: the covariance at `prec`, the
-    subspace in FP32, the spectrum in FP32 (FP32 plan) or with compensated
-    FP16 products (16-bit plan)."""
+    a plan at precision `prec` runs them: the covariance and the Method 2
+    sketch at `prec`, Method 1 in FP32, the spectrum in FP32 (FP32 plan) or
+    with compensated FP16 products (16-bit plan)."""
     s = fr.spec
     ctx.fm_covariance(fr.X, fr.R, prec, stream)
     if s.method == FM_METHOD_PROJECT:
         ctx.fm_subspace_project(fr.R, fr.Omega, s.q, s.K, fr.Us, fr.sigma, fr.status, s.rcond,
-                                0, stream)
+                                prec, stream)
     else:
         ctx.fm_subspace_sample(fr.R, fr.idx, s.K, fr.Us, fr.sigma, fr.status, s.rcond, stream)
     sprec = FM_FP32 if prec == FM_FP32 else FM_FP16

@@ -207,14 +207,14 @@ def test_peaks_many_local_maxima_fallback(ctx):
 # stage 2: subspace on the same covariance bits
 # ----------------------------------------------------------------------------
 
-def _subspace_case(ctx, R64, method, rnd, n, q, K):
+def _subspace_case(ctx, R64, method, rnd, n, q, K, prec=fm.FM_FP32):
     M = R64.shape[0]
     Rd = dev(R64.astype(np.complex64))
     Us = torch.zeros((K, M), dtype=torch.complex128, device="cuda")
     sig = torch.zeros(K, dtype=torch.float64, device="cuda")
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     if method == "project":
-        ctx.fm_subspace_project(Rd, dev(rnd), q, K, Us, sig, st)
+        ctx.fm_subspace_project(Rd, dev(rnd), q, K, Us, sig, st, prec=prec)
     else:
         ctx.fm_subspace_sample(Rd, dev(rnd), K, Us, sig, st)
     torch.cuda.synchronize()
@@ -227,20 +227,25 @@ def _subspace_case(ctx, R64, method, rnd, n, q, K):
     return Us.cpu().numpy(), sig.cpu().numpy(), int(st.cpu()[0]), Uo, so
 
 
-@pytest.mark.parametrize("name,method", [("c1", "project"), ("c1", "sample"),
-                                         ("c2", "project"), ("c2", "sample")])
-def test_subspace_matches_oracle(ctx, name, method):
+# The compensated FP16 sketch (hi + lo operands, ~22-bit products) is held
+# to the same bars as the FP32 one.
+@pytest.mark.parametrize("name,method,prec", [("c1", "project", "fp32"), ("c1", "sample", "fp32"),
+                                              ("c2", "project", "fp32"), ("c2", "sample", "fp32"),
+                                              ("c1", "project", "fp16"), ("c2", "project", "fp16")])
+def test_subspace_matches_oracle(ctx, name, method, prec):
     cfg = fmsynth.CONFIGS[name]
-    say(f"subspace {name} {method}")
+    say(f"subspace {name} {method} {prec}")
     fr, _ = fmsynth.config_frame(name, seed=23)
     R = oracle.covariance(fr.X, threads=oracle.default_threads())
     if method == "project":
         rnd, n = fmsynth.make_omega(fr.M, cfg["l"], 23), cfg["l"]
     else:
         rnd, n = fmsynth.make_idx(fr.M, cfg["p"], 23), cfg["p"]
-    Ug, sg, st, Uo, so = _subspace_case(ctx, R, method, rnd, n, cfg["q"], fr.K)
+    Ug, sg, st, Uo, so = _subspace_case(ctx, R, method, rnd, n, cfg["q"], fr.K,
+                                        SPEC_PRECS[prec])
     assert st == 0
     assert np.max(np.abs(Ug.conj() @ Ug.T - np.eye(fr.K))) <= 1e-9
+    say(f"  projector distance {np.linalg.norm(proj(Ug) - proj(Uo), 2):.3g}")
     assert np.linalg.norm(proj(Ug) - proj(Uo), 2) <= 1e-6
     assert np.max(np.abs(sg - so) / so) <= 1e-6
     th0, dth, L = fmsynth.grid(cfg["L"])
@@ -252,13 +257,17 @@ def test_subspace_matches_oracle(ctx, name, method):
 @pytest.mark.parametrize("M,K,n,q,method", [
     (40, 3, 3, 0, "project"), (40, 3, 40, 1, "project"), (97, 1, 9, 3, "project"),
     (65, 6, 64, 2, "project"), (40, 4, 40, 0, "sample"), (150, 5, 96, 0, "sample"),
-    (300, 7, 160, 0, "sample"), (33, 2, 2, 0, "sample")])
+    (300, 7, 160, 0, "sample"), (33, 2, 2, 0, "sample"),
+    (40, 3, 3, 0, "project16"), (40, 3, 40, 1, "project16"), (97, 1, 9, 3, "project16"),
+    (130, 6, 32, 2, "project16"), (65, 6, 64, 2, "project16"), (33, 5, 17, 1, "project16")])
 def test_subspace_edge_shapes(ctx, M, K, n, q, method):
     say(f"subspace edge M={M} K={K} n={n} q={q} {method}")
     fr = fmsynth.make_frame(M, 2 * M, K, 10.0, seed=M + n, angle_range=(-60, 60), min_sep=3)
     R = oracle.covariance(fr.X)
+    prec = fm.FM_FP16 if method == "project16" else fm.FM_FP32
+    method = "project" if method == "project16" else method
     rnd = fmsynth.make_omega(M, n, M) if method == "project" else fmsynth.make_idx(M, n, M)
-    Ug, sg, st, Uo, so = _subspace_case(ctx, R, method, rnd, n, q, K)
+    Ug, sg, st, Uo, so = _subspace_case(ctx, R, method, rnd, n, q, K, prec)
     assert st == 0
     assert np.linalg.norm(proj(Ug) - proj(Uo), 2) <= 1e-5
     assert np.max(np.abs(sg - so) / so) <= 1e-5
@@ -406,8 +415,8 @@ def test_argument_validation(ctx):
         ctx.fm_pseudospectrum(Us, 0.0, -1.0, 10, P)             # dtheta <= 0
     assert e.value.status == fm.FM_E_ARG
     with pytest.raises(fm.FmError) as e:
-        ctx.fm_subspace_project(R, Om, 2, 3, Us, sig, st, prec=fm.FM_BF16)  # FP32 only
-    assert e.value.status == fm.FM_E_UNSUPPORTED
+        ctx.fm_subspace_project(R, Om, 2, 3, Us, sig, st, prec=7)        # no such precision
+    assert e.value.status == fm.FM_E_ARG
     with pytest.raises(fm.FmError) as e:
         ctx.fm_pseudospectrum(Us, 0.0, 1.0, 10, P, prec=fm.FM_BF16)  # FP32 or FP16 only
     assert e.value.status == fm.FM_E_UNSUPPORTED
