@@ -87,8 +87,11 @@ typedef enum {
 
 /* Subspace method of a frame in a plan. */
 typedef enum {
-  FM_METHOD_PROJECT = 0, /* Method 2, Alg. 2 */
-  FM_METHOD_SAMPLE = 1   /* Method 1, Alg. 1 */
+  FM_METHOD_PROJECT = 0,   /* Method 2, Alg. 2 */
+  FM_METHOD_SAMPLE = 1,    /* Method 1, Alg. 1 */
+  FM_METHOD_PROJECT_X = 2  /* Method 2 with every product R V formed as
+                              X (X^H V) / T: R is never computed (the frame's R
+                              may be null); see fm_subspace_project_x */
 } fm_method;
 
 /* per-frame device status bits */
@@ -174,6 +177,22 @@ fm_status fm_subspace_project(fm_ctx *ctx, void *stream, const void *R, int M, i
                               const float *Omega, int l, int q, int K, double rcond,
                               fm_prec prec, void *Us, double *sigma, uint32_t *status);
 
+/* Method 2 straight from the snapshots: the same algorithm as
+ * fm_subspace_project on R = X X^H / T (eqs. (2)-(3)), with every product
+ * R V evaluated as X (X^H V) / T, so R is never formed -- identical in exact
+ * arithmetic, (q+1) * 16 M T l real flops instead of 4 M^2 T for R, at the
+ * cost of two reads of X per product.
+ *   X      complex64 [M][ldx] snapshots (as fm_covariance)
+ *   prec   FM_FP32 only (FM_E_UNSUPPORTED otherwise)
+ *   other arguments as fm_subspace_project
+ * Requires T >= 1, ldx >= T and the fm_subspace_project limits.  Uses
+ * workspace: fm_workspace_bytes(M, l, K, 0) plus T * l * 8 bytes (rounded up
+ * to 256). */
+fm_status fm_subspace_project_x(fm_ctx *ctx, void *stream, const void *X, int M, int T,
+                                int64_t ldx, const float *Omega, int l, int q, int K,
+                                double rcond, fm_prec prec, void *Us, double *sigma,
+                                uint32_t *status);
+
 /* ------------------------------------------------------------------------ */
 /* stage 3: pseudo-spectrum, eqs. (5) and (10)                               */
 /* ------------------------------------------------------------------------ */
@@ -216,7 +235,8 @@ typedef struct {
   const void *X;      /* complex64 [M][ldx] snapshots */
   int64_t ldx;
   int M, T;
-  void *R;            /* complex64 [M][ldr] covariance (written by stage 1) */
+  void *R;            /* complex64 [M][ldr] covariance (written by stage 1;
+                         not used, may be null, for FM_METHOD_PROJECT_X) */
   int64_t ldr;
   int K;              /* number of sources */
   int method;         /* fm_method */

@@ -83,8 +83,8 @@ struct fm_plan {
 
 namespace {
 
-enum Kind { kCov, kOmega, kGather, kSketch, kSketch16, kGram, kSmall, kApply, kSpecPrep, kSpec,
-             kSplit, kSpec16, kRefine,
+enum Kind { kCov, kOmega, kGather, kSketch, kSketch16, kXhv, kXz, kGram, kSmall, kApply,
+             kSpecPrep, kSpec, kSplit, kSpec16, kRefine,
             kPeaks };
 
 fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
@@ -107,16 +107,20 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // per-frame workspace layout (shared by single-frame calls and plans)
 struct WsLayout {
-  size_t y, v, part, small, uf, rlist, total;
+  size_t y, v, z, part, small, uf, rlist, total;
+  bool has_z;
 };
 
-WsLayout ws_layout(int M, int n, int K, int L) {
+// Tz > 0: Method 2 from X, with the [T][n] product X^H V
+WsLayout ws_layout(int M, int n, int K, int L, int Tz = 0) {
   const int np = (n + 1) & ~1;
   const int nchunk = (M + fm::kGramRows - 1) / fm::kGramRows;
   WsLayout w;
   size_t o = 0;
   w.y = o;     o += align256((size_t)M * n * 8);
   w.v = o;     o += align256((size_t)M * n * 8);
+  w.z = o;     o += align256((size_t)Tz * n * 8);
+  w.has_z = Tz > 0;
   w.part = o;  o += align256((size_t)nchunk * 2 * n * n * 16);
   w.small = o; o += align256(((size_t)fm::kSmallSlots * np * np + 1) * 16);
   w.uf = o;    o += align256((size_t)M * K * 8);
@@ -128,6 +132,7 @@ WsLayout ws_layout(int M, int n, int K, int L) {
 void bind_ws(FrameDev &f, char *base, const WsLayout &w) {
   f.Y = reinterpret_cast<float2 *>(base + w.y);
   f.V = reinterpret_cast<float2 *>(base + w.v);
+  f.Z = w.has_z ? reinterpret_cast<float2 *>(base + w.z) : nullptr;
   f.part = reinterpret_cast<double2 *>(base + w.part);
   f.small = reinterpret_cast<double2 *>(base + w.small);
   f.Uf = reinterpret_cast<float2 *>(base + w.uf);
@@ -177,7 +182,7 @@ fm_status check_sub(fm_ctx *c, const void *R, int M, int64_t ldr, int method, in
     return fail(c, FM_E_ARG, "subspace: need 1 <= K <= n <= M (K=%d n=%d M=%d)", K, n, M);
   if (K > fm::kMaxK) return fail(c, FM_E_UNSUPPORTED, "subspace: K=%d > %d", K, fm::kMaxK);
   if (!(rcond >= 0.0) || !std::isfinite(rcond)) return fail(c, FM_E_ARG, "subspace: bad rcond");
-  if (method == FM_METHOD_PROJECT) {
+  if (method == FM_METHOD_PROJECT || method == FM_METHOD_PROJECT_X) {
     if (n > fm::kMaxL) return fail(c, FM_E_UNSUPPORTED, "subspace_project: l=%d > %d", n, fm::kMaxL);
     if (q < 0 || q > 16) return fail(c, FM_E_ARG, "subspace_project: need 0 <= q <= 16 (q=%d)", q);
   } else if (method == FM_METHOD_SAMPLE) {
@@ -218,8 +223,13 @@ int sketch_nb(int n) { return (2 * n + 31) / 32; }
 hipError_t run_project_single(FrameDev &f, hipStream_t s, fm_prec prec) {
   hipError_t e;
   const int nb = sketch_nb(f.n);
-  const bool s16 = prec != FM_FP32 && fm::sketch16_ok(nb);
-  auto sketch = [&](int r) {
+  const bool from_x = f.method == FM_METHOD_PROJECT_X;
+  const bool s16 = !from_x && prec != FM_FP32 && fm::sketch16_ok(nb);
+  auto sketch = [&](int r) -> hipError_t {
+    if (from_x) {
+      hipError_t e2 = fm::launch_xhv(f, nullptr, nullptr, 0, nb, s);
+      return e2 != hipSuccess ? e2 : fm::launch_xz(f, nullptr, nullptr, 0, nb, r, s);
+    }
     return s16 ? fm::launch_sketch16(f, nullptr, nullptr, 0, nb, r, s)
                : fm::launch_sketch(f, nullptr, nullptr, 0, nb, r, s);
   };
@@ -387,6 +397,46 @@ static fm_status subspace_single(fm_ctx *ctx, void *stream, const void *R, int M
   return FM_OK;
 }
 
+FM_API fm_status fm_subspace_project_x(fm_ctx *ctx, void *stream, const void *X, int M, int T,
+                                       int64_t ldx, const float *Omega, int l, int q, int K,
+                                       double rcond, fm_prec prec, void *Us, double *sigma,
+                                       uint32_t *status) {
+  if (!ctx) return FM_E_ARG;
+  if (!X) return fail(ctx, FM_E_ARG, "subspace_project_x: null X");
+  if (T < 1 || ldx < T)
+    return fail(ctx, FM_E_ARG, "subspace_project_x: need T >= 1 and ldx >= T (T=%d ldx=%lld)", T,
+                (long long)ldx);
+  fm_status st = check_sub(ctx, X, M, M, FM_METHOD_PROJECT_X, l, q, K, rcond, Omega, Us, sigma,
+                           status);
+  if (st != FM_OK) return st;
+  if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "subspace_project_x: bad precision %d", (int)prec);
+  if (prec != FM_FP32)
+    return fail(ctx, FM_E_UNSUPPORTED, "subspace_project_x: FM_FP32 products only");
+  const WsLayout w = ws_layout(M, l, K, 0, T);
+  if (w.total > ctx->arena_bytes)
+    return fail(ctx, FM_E_WORKSPACE, "subspace_project_x: needs %zu arena bytes, have %zu",
+                w.total, ctx->arena_bytes);
+  if ((st = set_dev(ctx)) != FM_OK) return st;
+  FrameDev f = blank_frame();
+  f.X = static_cast<const float2 *>(X);
+  f.ldx = ldx;
+  f.M = M;
+  f.T = T;
+  f.K = K;
+  f.method = FM_METHOD_PROJECT_X;
+  f.n = l;
+  f.q = q;
+  f.rcond = rcond;
+  f.Omega = Omega;
+  f.Us = static_cast<double2 *>(Us);
+  f.sigma = sigma;
+  f.status = status;
+  bind_ws(f, ctx->arena, w);
+  hipError_t e = run_project_single(f, (hipStream_t)stream, prec);
+  if (e != hipSuccess) return hip_fail(ctx, e, "subspace_project_x launch");
+  return FM_OK;
+}
+
 FM_API fm_status fm_subspace_sample(fm_ctx *ctx, void *stream, const void *R, int M,
                                     int64_t ldr, const int32_t *idx, int p, int K, double rcond,
                                     void *Us, double *sigma, uint32_t *status) {
@@ -476,6 +526,8 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kGather: return fm::launch_gather(cls, fr, it, L.count, s);
     case kSketch: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, L.mode, s);
     case kSketch16: return fm::launch_sketch16(cls, fr, it, L.count, L.n_class, L.mode, s);
+    case kXhv: return fm::launch_xhv(cls, fr, it, L.count, L.n_class, s);
+    case kXz: return fm::launch_xz(cls, fr, it, L.count, L.n_class, L.mode, s);
     case kGram: return fm::launch_gram(cls, fr, it, L.count, L.mode, s);
     case kSmall: return fm::launch_small(cls, fr, it, L.count, L.mode, s);
     case kApply: return fm::launch_apply(cls, fr, it, L.count, L.mode, s);
@@ -512,10 +564,14 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "plan: bad precision %d", (int)prec);
   for (int i = 0; i < n_frames; ++i) {
     const fm_frame &a = frames[i];
-    fm_status st = check_cov(ctx, a.X, a.M, a.T, a.ldx, a.R, a.ldr);
+    // Method 2 from X forms no R: its R may be null
+    const bool from_x = a.method == FM_METHOD_PROJECT_X;
+    fm_status st = check_cov(ctx, a.X, a.M, a.T, a.ldx, from_x ? a.X : a.R,
+                             from_x ? a.M : a.ldr);
     if (st == FM_OK)
-      st = check_sub(ctx, a.R, a.M, a.ldr, a.method, a.n, a.q, a.K, a.rcond,
-                     a.method == FM_METHOD_PROJECT ? (const void *)a.Omega : (const void *)a.idx,
+      st = check_sub(ctx, from_x ? a.X : a.R, a.M, from_x ? a.M : a.ldr, a.method, a.n, a.q,
+                     a.K, a.rcond,
+                     a.method != FM_METHOD_SAMPLE ? (const void *)a.Omega : (const void *)a.idx,
                      a.Us, a.sigma, a.status);
     if (st == FM_OK) st = check_spec(ctx, a.Us, a.M, a.K, a.theta0_deg, a.dtheta_deg, a.L, a.P);
     if (st == FM_OK) st = check_peaks(ctx, a.P, a.L, a.K, a.peak_idx, a.peak_val, a.n_found);
@@ -538,7 +594,8 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   std::vector<size_t> off(n_frames);
   size_t total = 0;
   for (int i = 0; i < n_frames; ++i) {
-    lay[i] = ws_layout(frames[i].M, frames[i].n, frames[i].K, frames[i].L);
+    lay[i] = ws_layout(frames[i].M, frames[i].n, frames[i].K, frames[i].L,
+                       frames[i].method == FM_METHOD_PROJECT_X ? frames[i].T : 0);
     off[i] = total;
     total += lay[i].total;
   }
@@ -616,6 +673,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     std::vector<std::vector<Item>> q(kXcd);
     std::vector<double> load(kXcd, 0.0);
     for (int i : order) {
+      if (frames[i].method == FM_METHOD_PROJECT_X) continue;  // forms no R
       const int nt = (frames[i].M + fm::kCovTile - 1) / fm::kCovTile;
       if (ctx->knob[FM_KNOB_COV_SCHEDULE][cov_bucket(frames[i].M)] == 0) {
         // the whole frame onto the least-loaded XCD
@@ -658,7 +716,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   // stage 2 init: Omega -> V / Y (Method 2), gather (Method 1)
   b0 = begin();
   for (int i : order)
-    if (frames[i].method == FM_METHOD_PROJECT)
+    if (frames[i].method != FM_METHOD_SAMPLE)
       for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
   add(p->sub, kOmega, 0, 0, b0);
   b0 = begin();
@@ -670,7 +728,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   const int classes[4] = {16, 32, fm::kSmallLdsN, fm::kMaxN};
   // a sketch of a column class that fuses the Gram step leaves its partials
   auto fused = [&](int i) {
-    return frames[i].method == FM_METHOD_PROJECT && fm::sketch_fuses_gram(sketch_nb(frames[i].n));
+    return frames[i].method != FM_METHOD_SAMPLE && fm::sketch_fuses_gram(sketch_nb(frames[i].n));
   };
   // after_sketch: this orth follows a product (round >= 1)
   auto orth_round = [&](auto pred, bool after_sketch) {
@@ -691,20 +749,37 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
         for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
     add(p->sub, kApply, fm::kApplyV, 0, b);
   };
+  auto from_x = [&](int i) { return frames[i].method == FM_METHOD_PROJECT_X; };
   auto sketch_round = [&](auto pred, int round) {
     for (int nb = 1; nb <= 4; ++nb) {
       size_t b = begin();
       for (int i : order)
-        if (pred(i) && sketch_nb(frames[i].n) == nb)
+        if (pred(i) && !from_x(i) && sketch_nb(frames[i].n) == nb)
           for (int c = 0; c < rows(frames[i].M, fm::kSketchRows); ++c)
             items.push_back({i, c, 0, 0});
       add(p->sub, (prec != FM_FP32 && fm::sketch16_ok(nb)) ? kSketch16 : kSketch, round, nb, b);
     }
+    // without R: Z = X^H V for every such frame, then Y = X Z / T
+    for (int nb = 1; nb <= 4; ++nb) {
+      size_t b = begin();
+      for (int i : order)
+        if (pred(i) && from_x(i) && sketch_nb(frames[i].n) == nb)
+          for (int c = 0; c < rows(frames[i].T, fm::kXhvCols); ++c) items.push_back({i, c, 0, 0});
+      add(p->sub, kXhv, 0, nb, b);
+    }
+    for (int nb = 1; nb <= 4; ++nb) {
+      size_t b = begin();
+      for (int i : order)
+        if (pred(i) && from_x(i) && sketch_nb(frames[i].n) == nb)
+          for (int c = 0; c < rows(frames[i].M, fm::kSketchRows); ++c)
+            items.push_back({i, c, 0, 0});
+      add(p->sub, kXz, round, nb, b);
+    }
   };
   int qmax = 0;
   for (int i = 0; i < n_frames; ++i)
-    if (frames[i].method == FM_METHOD_PROJECT) qmax = std::max(qmax, frames[i].q);
-  auto is_proj = [&](int i) { return frames[i].method == FM_METHOD_PROJECT; };
+    if (frames[i].method != FM_METHOD_SAMPLE) qmax = std::max(qmax, frames[i].q);
+  auto is_proj = [&](int i) { return frames[i].method != FM_METHOD_SAMPLE; };
   // round 0: orth(Omega) for q = 0 frames, then the first product for all
   orth_round([&](int i) { return is_proj(i) && frames[i].q == 0; }, false);
   sketch_round(is_proj, 0);

@@ -46,6 +46,7 @@ struct FrameDev {
   // workspace (device)
   float2 *Y;            // [M][n] sketch C (= R V, or gathered columns)
   float2 *V;            // [M][n] orthonormal basis fed to the next product
+  float2 *Z;            // [T][n] X^H V (products with R formed from X, no R)
   double2 *part;        // [nchunk][2][n][n] Gram partial sums
   double2 *small;       // small dense scratch, kSmallSlots * npad^2
   float2 *Uf;           // FP32 pass: [M][K] FP32 copy of U_s; FP16 pass: scaled
@@ -105,6 +106,14 @@ inline bool sketch_fuses_gram(int nb) { return nb <= 2; }
 hipError_t launch_sketch16(const FrameDev &single, const FrameDev *frames, const Item *items,
                            int n_items, int nb, int round, hipStream_t s);
 inline bool sketch16_ok(int nb) { return nb <= 2; }
+// products with R without forming it (Method 2 from X): R V = X (X^H V) / T.
+// launch_xhv: Z = X^H V (one workgroup per 128 snapshots); launch_xz:
+// Y = X Z / T, Gram partials as launch_sketch (one workgroup per 128 rows)
+hipError_t launch_xhv(const FrameDev &single, const FrameDev *frames, const Item *items,
+                      int n_items, int nb, hipStream_t s);
+hipError_t launch_xz(const FrameDev &single, const FrameDev *frames, const Item *items,
+                     int n_items, int nb, int round, hipStream_t s);
+constexpr int kXhvCols = 128;  // snapshots per xhv workgroup
 hipError_t launch_gather(const FrameDev &single, const FrameDev *frames, const Item *items,
                          int n_items, hipStream_t s);
 hipError_t launch_gram(const FrameDev &single, const FrameDev *frames, const Item *items,

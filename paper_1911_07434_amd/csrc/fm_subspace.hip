@@ -103,8 +103,14 @@ typedef FM_GLOBAL const float2 gfloat2;
 
 // SK = elements of its row each lane holds per chunk (chunk = 2 SK columns);
 // wide column classes use SK = 8 to stay within the register file
+// Y = scale * A B with A [M][kdim] (leading dimension lda) and B [kdim][n]:
+// the products with R (A = R, B = V, kdim = M, scale 1) and, without forming
+// R, the second half of R V = X (X^H V) / T (A = X, B = Z, kdim = T,
+// scale 1/T).
 template <int NB, int SK>
 __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk, int gmode,
+                                            const float2 *Am, long long lda, int kdim,
+                                            const float2 *Bm, float scale,
                                             float2 (*vbuf)[kSkChunkMax * kMaxL]) {
   constexpr int kSkChunk = 2 * SK;
   const int tid = threadIdx.x;
@@ -112,7 +118,7 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
   const int r = lane & 31, h = lane >> 5;
   const int M = f.M, n = f.n;
   const int row = min(i0 + r, M - 1);
-  const gfloat2 *pr = (const gfloat2 *)(f.R + (size_t)row * f.ldr + SK * h);
+  const gfloat2 *pr = (const gfloat2 *)(Am + (size_t)row * lda + SK * h);
   int col[NB], part[NB];
   bool okc[NB];
 #pragma unroll
@@ -128,9 +134,9 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
 
-  const int nchunk = (M + kSkChunk - 1) / kSkChunk;
+  const int nchunk = (kdim + kSkChunk - 1) / kSkChunk;
   const int velems = kSkChunk * n;  // <= 32 * 64 = 2048 -> at most 8 per thread
-  const gfloat2 *V = (const gfloat2 *)f.V;
+  const gfloat2 *V = (const gfloat2 *)Bm;
   float2 vst[8];
   auto load_v = [&](int c) {
 #pragma unroll
@@ -138,7 +144,7 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
       const int e = tid + 256 * j;
       const int m = c * kSkChunk + e / n;
       vst[j] = make_float2(0.f, 0.f);
-      if (e < velems && m < M) vst[j] = V[(size_t)c * kSkChunk * n + e];
+      if (e < velems && m < kdim) vst[j] = V[(size_t)c * kSkChunk * n + e];
     }
   };
   auto store_v = [&](int buf) {
@@ -148,17 +154,17 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
       if (e < velems) vbuf[buf][e] = vst[j];
     }
   };
-  // R chunk c: SK elements of this lane's row; columns past M read as zero
+  // A chunk c: SK elements of this lane's row; columns past kdim read as zero
   auto load_r = [&](float2 (&a)[SK], int c) {
     const int m0 = c * kSkChunk + SK * h;
-    if (m0 + SK <= M) {
+    if (m0 + SK <= kdim) {
 #pragma unroll
       for (int s = 0; s < SK; ++s) a[s] = pr[c * kSkChunk + s];
     } else {
 #pragma unroll
       for (int s = 0; s < SK; ++s) {
         a[s] = make_float2(0.f, 0.f);
-        if (m0 + s < M) a[s] = pr[c * kSkChunk + s];
+        if (m0 + s < kdim) a[s] = pr[c * kSkChunk + s];
       }
     }
   };
@@ -200,6 +206,12 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
     compute(a1, vbuf[1]);
     if (has2) store_v(0);
     __syncthreads();
+  }
+  if (scale != 1.f) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[b][v] *= scale;
   }
   float *Yf = reinterpret_cast<float *>(f.Y);
 #pragma unroll
@@ -254,7 +266,146 @@ __global__ __launch_bounds__(256) void sketch_kernel(FrameDev single, const Fram
   // rows start past M clamp to row M-1 and store nothing
   const int i0 = blk * kSketchRows + (threadIdx.x >> 6) * 32;
   const int gmode = round < 0 ? -1 : (round < f.q ? kGramSelf : kGramFinal);
-  sketch_rows<NB, (NB <= 2 ? 16 : 8)>(f, i0, blk, gmode, vbuf);
+  sketch_rows<NB, (NB <= 2 ? 16 : 8)>(f, i0, blk, gmode, f.R, f.ldr, f.M, f.V, 1.f, vbuf);
+}
+
+// ---------------------------------------------------------------------------
+// products with R without forming R: R V = X (X^H V) / T
+// ---------------------------------------------------------------------------
+// Z = X^H V, Z[t][c] = sum_m conj(X[m][t]) V[m][c].  One wave = 32 snapshots
+// t (the MFMA rows), all 2n real output columns; the contraction runs over
+// the channels m two at a time (one per half-wave), so the lanes of a wave
+// read two rows of X at 32 consecutive snapshots -- contiguous 256 bytes.
+//   Re Z = Xr Vr + Xi Vi,   Im Z = Xr Vi - Xi Vr.
+// V chunks are staged in LDS as in the sketch; X is prefetched a chunk ahead.
+template <int NB>
+__device__ __forceinline__ void xhv_cols(const FrameDev &f, int t0w,
+                                         float2 (*vbuf)[kSkChunkMax * kMaxL]) {
+  constexpr int kCh = 32, kSteps = kCh / 2;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int r = lane & 31, h = lane >> 5;
+  const int M = f.M, T = f.T, n = f.n;
+  const int t = min(t0w + r, T - 1);
+  const gfloat2 *px = (const gfloat2 *)(f.X + t);
+  const long long ldx = f.ldx;
+  int col[NB], part[NB];
+  bool okc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int nn = 32 * b + r;
+    okc[b] = nn < 2 * n;
+    part[b] = nn < n ? 0 : 1;
+    col[b] = okc[b] ? (nn < n ? nn : nn - n) : 0;
+  }
+  floatx16 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
+  const int nchunk = (M + kCh - 1) / kCh;
+  const int velems = kCh * n;
+  const gfloat2 *V = (const gfloat2 *)f.V;
+  float2 vst[8];
+  auto load_v = [&](int c) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      const int m = c * kCh + e / n;
+      vst[j] = make_float2(0.f, 0.f);
+      if (e < velems && m < M) vst[j] = V[(size_t)c * kCh * n + e];
+    }
+  };
+  auto store_v = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      if (e < velems) vbuf[buf][e] = vst[j];
+    }
+  };
+  // chunk c: step s holds X[m][t] for m = 32 c + 2 s + h; rows past M are zero
+  auto load_x = [&](float2 (&a)[kSteps], int c) {
+    const int m0 = c * kCh;
+    if (m0 + kCh <= M) {
+#pragma unroll
+      for (int s = 0; s < kSteps; ++s) a[s] = px[(size_t)(m0 + 2 * s + h) * ldx];
+    } else {
+#pragma unroll
+      for (int s = 0; s < kSteps; ++s) {
+        const int m = m0 + 2 * s + h;
+        a[s] = make_float2(0.f, 0.f);
+        if (m < M) a[s] = px[(size_t)m * ldx];
+      }
+    }
+  };
+  auto compute = [&](const float2 (&a)[kSteps], const float2 *vb) {
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float2 v = okc[b] ? vb[(2 * s + h) * n + col[b]] : make_float2(0.f, 0.f);
+        const float b1 = part[b] == 0 ? v.x : v.y;    // with Xr
+        const float b2 = part[b] == 0 ? v.y : -v.x;   // with Xi
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s].x, b1, acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s].y, b2, acc[b], 0, 0, 0);
+      }
+    }
+  };
+  float2 a0[kSteps], a1[kSteps];
+  load_v(0);
+  store_v(0);
+  load_x(a0, 0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; c += 2) {
+    const bool has1 = c + 1 < nchunk;
+    if (has1) {
+      load_v(c + 1);
+      load_x(a1, c + 1);
+    }
+    compute(a0, vbuf[0]);
+    if (has1) store_v(1);
+    __syncthreads();
+    if (!has1) break;
+    const bool has2 = c + 2 < nchunk;
+    if (has2) {
+      load_v(c + 2);
+      load_x(a0, c + 2);
+    }
+    compute(a1, vbuf[1]);
+    if (has2) store_v(0);
+    __syncthreads();
+  }
+  float *Zf = reinterpret_cast<float *>(f.Z);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if (!okc[b]) continue;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int tt = t0w + (v >> 2) * 8 + h * 4 + (v & 3);
+      if (tt < T) Zf[((size_t)tt * n + col[b]) * 2 + part[b]] = acc[b][v];
+    }
+  }
+}
+
+template <int NB, bool kBatched>
+__global__ __launch_bounds__(256) void xhv_kernel(FrameDev single, const FrameDev *frames,
+                                                  const Item *items) {
+  __shared__ float2 vbuf[2][kSkChunkMax * kMaxL];
+  int blk, unused;
+  const FrameDev &f = frame_of<kBatched>(single, frames, items, blk, unused);
+  xhv_cols<NB>(f, blk * kXhvCols + (threadIdx.x >> 6) * 32, vbuf);
+}
+
+template <int NB, bool kBatched>
+__global__ __launch_bounds__(256) void xz_kernel(FrameDev single, const FrameDev *frames,
+                                                 const Item *items, int round) {
+  __shared__ float2 vbuf[2][kSkChunkMax * kMaxL];
+  int blk, unused;
+  const FrameDev &f = frame_of<kBatched>(single, frames, items, blk, unused);
+  const int i0 = blk * kSketchRows + (threadIdx.x >> 6) * 32;
+  const int gmode = round < 0 ? -1 : (round < f.q ? kGramSelf : kGramFinal);
+  sketch_rows<NB, (NB <= 2 ? 16 : 8)>(f, i0, blk, gmode, f.X, f.ldx, f.T, f.Z,
+                                      1.f / (float)f.T, vbuf);
 }
 
 // ---------------------------------------------------------------------------
@@ -356,7 +507,7 @@ __global__ __launch_bounds__(256) void gram_kernel(FrameDev single, const FrameD
   };
   if (mode == kGramSelf) {
     run(f.Y, f.Y, p0);
-  } else if (f.method == FM_METHOD_PROJECT) {
+  } else if (f.method != FM_METHOD_SAMPLE) {
     run(f.V, f.Y, p0);   // core = V^H (R V)
     run(f.Y, f.Y, p1);   // C^H C
   } else {
@@ -768,6 +919,39 @@ hipError_t launch_sketch(const FrameDev &single, const FrameDev *frames, const I
     default: FM_SK(4); break;
   }
 #undef FM_SK
+  return hipGetLastError();
+}
+
+hipError_t launch_xhv(const FrameDev &single, const FrameDev *frames, const Item *items,
+                      int n_items, int nb, hipStream_t s) {
+  const dim3 g(items ? n_items : (single.T + kXhvCols - 1) / kXhvCols), b(256);
+#define FM_XH(NB)                                                                            \
+  if (items) hipLaunchKernelGGL((xhv_kernel<NB, true>), g, b, 0, s, single, frames, items);  \
+  else hipLaunchKernelGGL((xhv_kernel<NB, false>), g, b, 0, s, single, frames, items);
+  switch (nb) {
+    case 1: FM_XH(1); break;
+    case 2: FM_XH(2); break;
+    case 3: FM_XH(3); break;
+    default: FM_XH(4); break;
+  }
+#undef FM_XH
+  return hipGetLastError();
+}
+
+hipError_t launch_xz(const FrameDev &single, const FrameDev *frames, const Item *items,
+                     int n_items, int nb, int round, hipStream_t s) {
+  const dim3 g(items ? n_items : (single.M + kSketchRows - 1) / kSketchRows), b(256);
+  const int rd = nb <= 2 ? round : -1;
+#define FM_XZ(NB)                                                                                \
+  if (items) hipLaunchKernelGGL((xz_kernel<NB, true>), g, b, 0, s, single, frames, items, rd);  \
+  else hipLaunchKernelGGL((xz_kernel<NB, false>), g, b, 0, s, single, frames, items, rd);
+  switch (nb) {
+    case 1: FM_XZ(1); break;
+    case 2: FM_XZ(2); break;
+    case 3: FM_XZ(3); break;
+    default: FM_XZ(4); break;
+  }
+#undef FM_XZ
   return hipGetLastError();
 }
 

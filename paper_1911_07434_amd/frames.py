@@ -10,7 +10,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import FM_FP16, FM_FP32, FM_METHOD_PROJECT, FM_METHOD_SAMPLE, FM_RCOND_DEFAULT, fm_frame
+from . import (FM_FP16, FM_FP32, FM_METHOD_PROJECT, FM_METHOD_PROJECT_X, FM_METHOD_SAMPLE,
+               FM_RCOND_DEFAULT, fm_frame)
 
 
 @dataclass
@@ -36,7 +37,7 @@ class DeviceFrame:
         self.X = (torch.as_tensor(X).to(dev) if X is not None
                   else torch.empty((s.M, s.T), dtype=torch.complex64, device=dev))
         self.R = torch.empty((s.M, s.M), dtype=torch.complex64, device=dev)
-        if s.method == FM_METHOD_PROJECT:
+        if s.method != FM_METHOD_SAMPLE:
             self.Omega = (torch.as_tensor(rnd).to(dev) if rnd is not None
                           else torch.empty((s.M, s.n), dtype=torch.float32, device=dev))
             self.idx = None
@@ -87,14 +88,20 @@ class DeviceFrame:
 def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
     """All four stages of one frame through the single-frame entry points, as
     a plan at precision `prec` runs them: the covariance and the Method 2
-    sketch at `prec`, Method 1 in FP32, the spectrum in FP32 (FP32 plan) or
-    with compensated FP16 products (16-bit plan)."""
+    sketch at `prec`, Method 1 and Method 2 from X (no covariance) in FP32,
+    the spectrum in FP32 (FP32 plan) or with compensated FP16 products
+    (16-bit plan)."""
     s = fr.spec
-    ctx.fm_covariance(fr.X, fr.R, prec, stream)
+    if s.method == FM_METHOD_PROJECT_X:
+        # Method 2 from the snapshots: no covariance (FP32 products)
+        ctx.fm_subspace_project_x(fr.X, fr.Omega, s.q, s.K, fr.Us, fr.sigma, fr.status, s.rcond,
+                                  FM_FP32, stream)
+    else:
+        ctx.fm_covariance(fr.X, fr.R, prec, stream)
     if s.method == FM_METHOD_PROJECT:
         ctx.fm_subspace_project(fr.R, fr.Omega, s.q, s.K, fr.Us, fr.sigma, fr.status, s.rcond,
                                 prec, stream)
-    else:
+    elif s.method == FM_METHOD_SAMPLE:
         ctx.fm_subspace_sample(fr.R, fr.idx, s.K, fr.Us, fr.sigma, fr.status, s.rcond, stream)
     sprec = FM_FP32 if prec == FM_FP32 else FM_FP16
     ctx.fm_pseudospectrum(fr.Us, s.theta0_deg, s.dtheta_deg, s.L, fr.P, sprec, stream)

@@ -273,6 +273,56 @@ def test_subspace_edge_shapes(ctx, M, K, n, q, method):
     assert np.max(np.abs(sg - so) / so) <= 1e-5
 
 
+# Method 2 without forming R: every product R V is X (X^H V) / T.  The oracle
+# is Method 2 on the FP64 covariance of the same complex64 X (the identity is
+# exact), so the bars are those of the FP32 Method 2 path.
+@pytest.mark.parametrize("M,T,K,n,q", [
+    (64, 128, 3, 11, 2), (1024, 2048, 8, 16, 2), (40, 80, 3, 3, 0), (97, 50, 1, 9, 3),
+    (130, 333, 6, 32, 2), (65, 100, 6, 64, 1), (200, 31, 4, 12, 2), (256, 4096, 5, 40, 0)])
+def test_subspace_from_x_matches_oracle(ctx, M, T, K, n, q):
+    say(f"subspace from X M={M} T={T} K={K} l={n} q={q}")
+    fr = fmsynth.make_frame(M, T, K, 10.0, seed=M + T, angle_range=(-60, 60), min_sep=2)
+    Om = fmsynth.make_omega(M, n, M + T)
+    Xd = dev(fr.X)
+    Us = torch.zeros((K, M), dtype=torch.complex128, device="cuda")
+    sig = torch.zeros(K, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.fm_subspace_project_x(Xd, dev(Om), q, K, Us, sig, st)
+    torch.cuda.synchronize()
+    R = oracle.covariance(fr.X, threads=oracle.default_threads())
+    Uo, so, _ = oracle.subspace_project(R, Om, q, K)
+    Ug, sg = Us.cpu().numpy(), sig.cpu().numpy()
+    d = np.linalg.norm(proj(Ug) - proj(Uo), 2)
+    say(f"  projector distance {d:.3g}, sigma rel {np.max(np.abs(sg - so) / so):.3g}")
+    assert int(st.cpu()[0]) == 0
+    assert d <= 1e-5
+    assert np.max(np.abs(sg - so) / so) <= 1e-5
+    if M == 1024:
+        th0, dth, L = fmsynth.grid(18001)
+        Pg, _ = oracle.pseudospectrum(Ug, th0, dth, L, threads=oracle.default_threads())
+        Po, _ = oracle.pseudospectrum(Uo, th0, dth, L, threads=oracle.default_threads())
+        assert db_err(Pg, Po) <= DB_FP32
+
+
+def test_subspace_from_x_validation(ctx):
+    X = torch.zeros((16, 8), dtype=torch.complex64, device="cuda")
+    Om = torch.zeros((16, 4), dtype=torch.float32, device="cuda")
+    Us = torch.zeros((2, 16), dtype=torch.complex128, device="cuda")
+    sig = torch.zeros(2, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(fm.FmError) as e:
+        ctx.fm_subspace_project_x(X, Om, 1, 2, Us, sig, st, prec=fm.FM_FP16)
+    assert e.value.status == fm.FM_E_UNSUPPORTED
+    with pytest.raises(fm.FmError) as e:
+        ctx.fm_subspace_project_x(X, Om, 1, 5, Us, sig, st)          # K > l
+    assert e.value.status == fm.FM_E_ARG
+    small = fm.Context(0, 4096)
+    with pytest.raises(fm.FmError) as e:
+        small.fm_subspace_project_x(X, Om, 1, 2, Us, sig, st)       # arena too small
+    assert e.value.status == fm.FM_E_WORKSPACE
+    small.close()
+
+
 def test_subspace_noiseless_rank_k(ctx):
     # exactly rank-K covariance: both methods recover span(A) (Lemmas 5, 6)
     M, K = 128, 4
@@ -352,7 +402,8 @@ def _mixed_frames(n, seed):
         T = int(rng.integers(M // 2, 2 * M + 1))
         K = int(rng.integers(1, 9))
         l, p = fmsynth.sketch_sizes(M, K)
-        method = fm.FM_METHOD_SAMPLE if i % 3 == 2 else fm.FM_METHOD_PROJECT
+        method = (fm.FM_METHOD_SAMPLE if i % 3 == 2 else
+                  fm.FM_METHOD_PROJECT_X if i % 4 == 3 else fm.FM_METHOD_PROJECT)
         n_ = p if method == fm.FM_METHOD_SAMPLE else l
         q = int(rng.integers(0, 3))
         L = int(rng.choice([181, 1801, 3001]))
@@ -385,7 +436,8 @@ def test_batch_equals_alone_bitwise(ctx, use_graph):
         torch.cuda.synchronize()
         for a, d in zip(alone, devs):
             b = d.results()
-            assert np.array_equal(a["R"], b["R"])
+            if d.spec.method != fm.FM_METHOD_PROJECT_X:   # that method forms no R
+                assert np.array_equal(a["R"], b["R"])
             assert np.array_equal(a["Us"], b["Us"])
             assert np.array_equal(a["sigma"], b["sigma"])
             assert np.array_equal(a["P"], b["P"])
@@ -516,6 +568,7 @@ def test_mixed_plan_equals_single_calls_bitwise(ctx):
         torch.cuda.synchronize()
         for a, d in zip(alone, devs):
             b = d.results()
-            assert np.array_equal(a["R"], b["R"])
+            if d.spec.method != fm.FM_METHOD_PROJECT_X:   # that method forms no R
+                assert np.array_equal(a["R"], b["R"])
             assert np.array_equal(a["P"], b["P"])
         plan.close()
