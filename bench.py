@@ -283,7 +283,7 @@ def main():
     def make_frames(method):
         out = []
         for i in range(B):
-            if method == fm.FM_METHOD_PROJECT:
+            if method != fm.FM_METHOD_SAMPLE:
                 spec = FrameSpec(M=M, T=T, K=K, method=method, n=L_SKETCH, q=Q_ITERS, L=L_GRID,
                                  theta0_deg=th0, dtheta_deg=dth)
                 d = DeviceFrame(spec, X=X[i], rnd=Om[i])
@@ -414,6 +414,40 @@ def main():
             v1 = B * n1 / (time.perf_counter() - t0)
         log(f"Method 1: {v1:.1f} frames/s")
         del plan1, frames1
+
+        # ---- Method 2 without forming R (products X (X^H V) / T), FP32 -----
+        framesx = make_frames(fm.FM_METHOD_PROJECT_X)
+        planx = fm.Plan(ctx, [d.descriptor() for d in framesx])
+        with torch.cuda.stream(stream):
+            step(planx)
+            torch.cuda.synchronize()
+            nx = max(5, args.steps // 2)
+            evx = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(nx)]
+            t0 = time.perf_counter()
+            for sidx in range(nx):
+                step(planx, evx[sidx])
+            torch.cuda.synchronize()
+            vx = B * nx / (time.perf_counter() - t0)
+        smx = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evx]))
+               for i, n in enumerate(stage_names)}
+        # the same frames' spectra through both routes (identical in exact
+        # arithmetic): the covariance route rerun in FP32 on the first four
+        from paper_1911_07434_amd.frames import run_single
+        with torch.cuda.stream(stream):
+            for i in range(4):
+                run_single(ctx, frames2[i], fm.FM_FP32, stream)
+        torch.cuda.synchronize()
+        px = np.stack([framesx[i].P.cpu().numpy() for i in range(4)]).astype(np.float64)
+        p2 = np.stack([frames2[i].P.cpu().numpy() for i in range(4)]).astype(np.float64)
+        dbx = float(np.max(np.abs(10 * np.log10(px / p2))))
+        log(f"Method 2 without R: {vx:.1f} frames/s, stages {smx}, max |dP| vs R route {dbx:.2g} dB")
+        out["covariance_free"] = {
+            "frames_per_s": round(vx, 2),
+            "stage_ms_per_step": {k: round(v, 4) for k, v in smx.items()},
+            "products": "R V as X (X^H V) / T on FP32 MFMA, R never formed",
+            "max_abs_dP_db_vs_covariance_route_4_frames": dbx,
+        }
+        del planx, framesx
 
         # ---- standard MUSIC (full EVD) on the same GPU ---------------------
         nb = min(B, 32)
