@@ -283,7 +283,7 @@ def main():
     def make_frames(method):
         out = []
         for i in range(B):
-            if method != fm.FM_METHOD_SAMPLE:
+            if method in (fm.FM_METHOD_PROJECT, fm.FM_METHOD_PROJECT_X):
                 spec = FrameSpec(M=M, T=T, K=K, method=method, n=L_SKETCH, q=Q_ITERS, L=L_GRID,
                                  theta0_deg=th0, dtheta_deg=dth)
                 d = DeviceFrame(spec, X=X[i], rnd=Om[i])
@@ -414,6 +414,19 @@ def main():
             v1 = B * n1 / (time.perf_counter() - t0)
         log(f"Method 1: {v1:.1f} frames/s")
         del plan1, frames1
+        # Method 1 without forming R (C = X X(I, :)^H / T)
+        frames1x = make_frames(fm.FM_METHOD_SAMPLE_X)
+        plan1x = fm.Plan(ctx, [d.descriptor() for d in frames1x])
+        with torch.cuda.stream(stream):
+            step(plan1x)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n1):
+                step(plan1x)
+            torch.cuda.synchronize()
+            v1x = B * n1 / (time.perf_counter() - t0)
+        log(f"Method 1 without R: {v1x:.1f} frames/s")
+        del plan1x, frames1x
 
         # ---- Method 2 without forming R (products X (X^H V) / T), FP32 -----
         framesx = make_frames(fm.FM_METHOD_PROJECT_X)
@@ -443,6 +456,7 @@ def main():
         log(f"Method 2 without R: {vx:.1f} frames/s, stages {smx}, max |dP| vs R route {dbx:.2g} dB")
         out["covariance_free"] = {
             "frames_per_s": round(vx, 2),
+            "method1_frames_per_s": round(v1x, 2),
             "stage_ms_per_step": {k: round(v, 4) for k, v in smx.items()},
             "products": "R V as X (X^H V) / T on FP32 MFMA, R never formed",
             "max_abs_dP_db_vs_covariance_route_4_frames": dbx,

@@ -89,9 +89,12 @@ typedef enum {
 typedef enum {
   FM_METHOD_PROJECT = 0,   /* Method 2, Alg. 2 */
   FM_METHOD_SAMPLE = 1,    /* Method 1, Alg. 1 */
-  FM_METHOD_PROJECT_X = 2  /* Method 2 with every product R V formed as
+  FM_METHOD_PROJECT_X = 2, /* Method 2 with every product R V formed as
                               X (X^H V) / T: R is never computed (the frame's R
                               may be null); see fm_subspace_project_x */
+  FM_METHOD_SAMPLE_X = 3   /* Method 1 with C = R(:, I) formed as
+                              X X(I, :)^H / T: R is never computed (R may be
+                              null); see fm_subspace_sample_x */
 } fm_method;
 
 /* per-frame device status bits */
@@ -188,6 +191,18 @@ fm_status fm_subspace_project(fm_ctx *ctx, void *stream, const void *R, int M, i
  * Requires T >= 1, ldx >= T and the fm_subspace_project limits.  Uses
  * workspace: fm_workspace_bytes(M, l, K, 0) plus T * l * 8 bytes (rounded up
  * to 256). */
+/* Method 1 straight from the snapshots: the same algorithm as
+ * fm_subspace_sample on R = X X^H / T, with the sampled columns formed as
+ * C = R(:, I) = X X(I, :)^H / T and the core R(I, I) taken from C(I, :) --
+ * 8 M T p real flops instead of 4 M^2 T for R.
+ *   X      complex64 [M][ldx] snapshots
+ *   other arguments as fm_subspace_sample
+ * Requires T >= 1, ldx >= T, 1 <= K <= p <= min(M, 64).  Uses workspace:
+ * fm_workspace_bytes(M, p, K, 0) plus T * p * 8 bytes (rounded up to 256). */
+fm_status fm_subspace_sample_x(fm_ctx *ctx, void *stream, const void *X, int M, int T,
+                               int64_t ldx, const int32_t *idx, int p, int K, double rcond,
+                               void *Us, double *sigma, uint32_t *status);
+
 fm_status fm_subspace_project_x(fm_ctx *ctx, void *stream, const void *X, int M, int T,
                                 int64_t ldx, const float *Omega, int l, int q, int K,
                                 double rcond, fm_prec prec, void *Us, double *sigma,

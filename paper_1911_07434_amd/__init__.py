@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfastmusi
 
 FM_OK, FM_E_ARG, FM_E_HIP, FM_E_WORKSPACE, FM_E_UNSUPPORTED = 0, 1, 2, 3, 4
 FM_FP32, FM_BF16, FM_FP16 = 0, 1, 2
-FM_METHOD_PROJECT, FM_METHOD_SAMPLE, FM_METHOD_PROJECT_X = 0, 1, 2
+FM_METHOD_PROJECT, FM_METHOD_SAMPLE, FM_METHOD_PROJECT_X, FM_METHOD_SAMPLE_X = 0, 1, 2, 3
 FM_ST_NONFINITE, FM_ST_EIG_MAXIT, FM_ST_RANK_DEFICIENT, FM_ST_FEW_PEAKS, FM_ST_BAD_INDEX = (
     1, 4, 8, 16, 32)
 FM_RCOND_DEFAULT = 1e-6
@@ -31,7 +31,7 @@ EXPORTS = (
     "fm_peaks", "fm_plan_create", "fm_plan_destroy", "fm_plan_workspace_bytes",
     "fm_plan_covariance", "fm_plan_subspace", "fm_plan_pseudospectrum", "fm_plan_peaks",
     "fm_plan_run", "fm_plan_bytes", "fm_plan_create_in", "fm_set_knob", "fm_get_knob",
-    "fm_subspace_project_x",
+    "fm_subspace_project_x", "fm_subspace_sample_x",
 )
 
 
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "fm_plan_create_in": ([P, C.POINTER(fm_frame), I, I, P, Z, P, C.POINTER(P)], I),
         "fm_set_knob": ([P, I, I, I], I),
         "fm_subspace_project_x": ([P, P, P, I, I, I64, P, I, I, I, D, I, P, P, P], I),
+        "fm_subspace_sample_x": ([P, P, P, I, I, I64, P, I, I, D, P, P, P], I),
         "fm_get_knob": ([P, I, I], I),
     }
     for name, (args, res) in sig.items():
@@ -177,6 +178,13 @@ class Context:
                                                   X.stride(0), _ptr(Omega), Omega.shape[1], q,
                                                   K, rcond, prec, _ptr(Us), _ptr(sigma),
                                                   _ptr(status)))
+
+    def fm_subspace_sample_x(self, X, idx, K, Us, sigma, status, rcond=FM_RCOND_DEFAULT,
+                             stream=None):
+        M, T = X.shape
+        self.check(self.lib.fm_subspace_sample_x(self.h, _stream(stream), _ptr(X), M, T,
+                                                 X.stride(0), _ptr(idx), idx.shape[0], K, rcond,
+                                                 _ptr(Us), _ptr(sigma), _ptr(status)))
 
     def fm_pseudospectrum(self, Us, theta0_deg, dtheta_deg, L, P, prec=FM_FP32, stream=None):
         K, M = Us.shape

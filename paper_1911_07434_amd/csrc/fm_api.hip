@@ -83,7 +83,7 @@ struct fm_plan {
 
 namespace {
 
-enum Kind { kCov, kOmega, kGather, kSketch, kSketch16, kXhv, kXz, kGram, kSmall, kApply,
+enum Kind { kCov, kOmega, kGather, kSketch, kSketch16, kXhv, kXz, kZx, kXcore, kGram, kSmall, kApply,
              kSpecPrep, kSpec, kSplit, kSpec16, kRefine,
             kPeaks };
 
@@ -187,6 +187,8 @@ fm_status check_sub(fm_ctx *c, const void *R, int M, int64_t ldr, int method, in
     if (q < 0 || q > 16) return fail(c, FM_E_ARG, "subspace_project: need 0 <= q <= 16 (q=%d)", q);
   } else if (method == FM_METHOD_SAMPLE) {
     if (n > fm::kMaxN) return fail(c, FM_E_UNSUPPORTED, "subspace_sample: p=%d > %d", n, fm::kMaxN);
+  } else if (method == FM_METHOD_SAMPLE_X) {
+    if (n > fm::kMaxL) return fail(c, FM_E_UNSUPPORTED, "subspace_sample_x: p=%d > %d", n, fm::kMaxL);
   } else {
     return fail(c, FM_E_ARG, "subspace: unknown method %d", method);
   }
@@ -257,7 +259,13 @@ hipError_t run_project_single(FrameDev &f, hipStream_t s, fm_prec prec) {
 
 hipError_t run_sample_single(FrameDev &f, hipStream_t s) {
   hipError_t e;
-  if ((e = fm::launch_gather(f, nullptr, nullptr, 0, s)) != hipSuccess) return e;
+  if (f.method == FM_METHOD_SAMPLE_X) {
+    if ((e = fm::launch_zx(f, nullptr, nullptr, 0, s)) != hipSuccess) return e;
+    if ((e = fm::launch_xz(f, nullptr, nullptr, 0, sketch_nb(f.n), -1, s)) != hipSuccess) return e;
+    if ((e = fm::launch_xcore(f, nullptr, nullptr, 0, s)) != hipSuccess) return e;
+  } else if ((e = fm::launch_gather(f, nullptr, nullptr, 0, s)) != hipSuccess) {
+    return e;
+  }
   if ((e = fm::launch_gram(f, nullptr, nullptr, 0, fm::kGramFinal, s)) != hipSuccess) return e;
   if ((e = fm::launch_small(f, nullptr, nullptr, 0, fm::kFinal, s)) != hipSuccess) return e;
   return fm::launch_apply(f, nullptr, nullptr, 0, fm::kApplyUs, s);
@@ -392,8 +400,45 @@ static fm_status subspace_single(fm_ctx *ctx, void *stream, const void *R, int M
   f.status = status;
   bind_ws(f, ctx->arena, w);
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = method == FM_METHOD_PROJECT ? run_project_single(f, s, prec) : run_sample_single(f, s);
+  hipError_t e = method == FM_METHOD_PROJECT ? run_project_single(f, s, prec)
+                                             : run_sample_single(f, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "subspace launch");
+  return FM_OK;
+}
+
+FM_API fm_status fm_subspace_sample_x(fm_ctx *ctx, void *stream, const void *X, int M, int T,
+                                      int64_t ldx, const int32_t *idx, int p, int K, double rcond,
+                                      void *Us, double *sigma, uint32_t *status) {
+  if (!ctx) return FM_E_ARG;
+  if (!X) return fail(ctx, FM_E_ARG, "subspace_sample_x: null X");
+  if (T < 1 || ldx < T)
+    return fail(ctx, FM_E_ARG, "subspace_sample_x: need T >= 1 and ldx >= T (T=%d ldx=%lld)", T,
+                (long long)ldx);
+  fm_status st = check_sub(ctx, X, M, M, FM_METHOD_SAMPLE_X, p, 0, K, rcond, idx, Us, sigma,
+                           status);
+  if (st != FM_OK) return st;
+  const WsLayout w = ws_layout(M, p, K, 0, T);
+  if (w.total > ctx->arena_bytes)
+    return fail(ctx, FM_E_WORKSPACE, "subspace_sample_x: needs %zu arena bytes, have %zu",
+                w.total, ctx->arena_bytes);
+  if ((st = set_dev(ctx)) != FM_OK) return st;
+  FrameDev f = blank_frame();
+  f.X = static_cast<const float2 *>(X);
+  f.ldx = ldx;
+  f.M = M;
+  f.T = T;
+  f.K = K;
+  f.method = FM_METHOD_SAMPLE_X;
+  f.n = p;
+  f.q = 0;
+  f.rcond = rcond;
+  f.idx = idx;
+  f.Us = static_cast<double2 *>(Us);
+  f.sigma = sigma;
+  f.status = status;
+  bind_ws(f, ctx->arena, w);
+  hipError_t e = run_sample_single(f, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "subspace_sample_x launch");
   return FM_OK;
 }
 
@@ -528,6 +573,8 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kSketch16: return fm::launch_sketch16(cls, fr, it, L.count, L.n_class, L.mode, s);
     case kXhv: return fm::launch_xhv(cls, fr, it, L.count, L.n_class, s);
     case kXz: return fm::launch_xz(cls, fr, it, L.count, L.n_class, L.mode, s);
+    case kZx: return fm::launch_zx(cls, fr, it, L.count, s);
+    case kXcore: return fm::launch_xcore(cls, fr, it, L.count, s);
     case kGram: return fm::launch_gram(cls, fr, it, L.count, L.mode, s);
     case kSmall: return fm::launch_small(cls, fr, it, L.count, L.mode, s);
     case kApply: return fm::launch_apply(cls, fr, it, L.count, L.mode, s);
@@ -565,13 +612,14 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   for (int i = 0; i < n_frames; ++i) {
     const fm_frame &a = frames[i];
     // Method 2 from X forms no R: its R may be null
-    const bool from_x = a.method == FM_METHOD_PROJECT_X;
+    const bool from_x = a.method == FM_METHOD_PROJECT_X || a.method == FM_METHOD_SAMPLE_X;
     fm_status st = check_cov(ctx, a.X, a.M, a.T, a.ldx, from_x ? a.X : a.R,
                              from_x ? a.M : a.ldr);
     if (st == FM_OK)
       st = check_sub(ctx, from_x ? a.X : a.R, a.M, from_x ? a.M : a.ldr, a.method, a.n, a.q,
                      a.K, a.rcond,
-                     a.method != FM_METHOD_SAMPLE ? (const void *)a.Omega : (const void *)a.idx,
+                     (a.method == FM_METHOD_PROJECT || a.method == FM_METHOD_PROJECT_X)
+                         ? (const void *)a.Omega : (const void *)a.idx,
                      a.Us, a.sigma, a.status);
     if (st == FM_OK) st = check_spec(ctx, a.Us, a.M, a.K, a.theta0_deg, a.dtheta_deg, a.L, a.P);
     if (st == FM_OK) st = check_peaks(ctx, a.P, a.L, a.K, a.peak_idx, a.peak_val, a.n_found);
@@ -594,8 +642,10 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   std::vector<size_t> off(n_frames);
   size_t total = 0;
   for (int i = 0; i < n_frames; ++i) {
+    const bool fx = frames[i].method == FM_METHOD_PROJECT_X ||
+                    frames[i].method == FM_METHOD_SAMPLE_X;
     lay[i] = ws_layout(frames[i].M, frames[i].n, frames[i].K, frames[i].L,
-                       frames[i].method == FM_METHOD_PROJECT_X ? frames[i].T : 0);
+                       fx ? frames[i].T : 0);
     off[i] = total;
     total += lay[i].total;
   }
@@ -673,7 +723,8 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     std::vector<std::vector<Item>> q(kXcd);
     std::vector<double> load(kXcd, 0.0);
     for (int i : order) {
-      if (frames[i].method == FM_METHOD_PROJECT_X) continue;  // forms no R
+      if (frames[i].method == FM_METHOD_PROJECT_X || frames[i].method == FM_METHOD_SAMPLE_X)
+        continue;  // forms no R
       const int nt = (frames[i].M + fm::kCovTile - 1) / fm::kCovTile;
       if (ctx->knob[FM_KNOB_COV_SCHEDULE][cov_bucket(frames[i].M)] == 0) {
         // the whole frame onto the least-loaded XCD
@@ -715,8 +766,11 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
 
   // stage 2 init: Omega -> V / Y (Method 2), gather (Method 1)
   b0 = begin();
+  auto is_proj = [&](int i) {
+    return frames[i].method == FM_METHOD_PROJECT || frames[i].method == FM_METHOD_PROJECT_X;
+  };
   for (int i : order)
-    if (frames[i].method != FM_METHOD_SAMPLE)
+    if (is_proj(i))
       for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
   add(p->sub, kOmega, 0, 0, b0);
   b0 = begin();
@@ -724,12 +778,28 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     if (frames[i].method == FM_METHOD_SAMPLE)
       for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
   add(p->sub, kGather, 0, 0, b0);
+  // Method 1 without R: Z = conj(X(I, :))^T, C = X Z / T, core = C(I, :)
+  auto sample_x = [&](int i) { return frames[i].method == FM_METHOD_SAMPLE_X; };
+  b0 = begin();
+  for (int i : order)
+    if (sample_x(i))
+      for (int c = 0; c < rows(frames[i].T, fm::kZxCols); ++c) items.push_back({i, c, 0, 0});
+  add(p->sub, kZx, 0, 0, b0);
+  for (int nb = 1; nb <= 4; ++nb) {
+    b0 = begin();
+    for (int i : order)
+      if (sample_x(i) && sketch_nb(frames[i].n) == nb)
+        for (int c = 0; c < rows(frames[i].M, fm::kSketchRows); ++c) items.push_back({i, c, 0, 0});
+    add(p->sub, kXz, -1, nb, b0);
+  }
+  b0 = begin();
+  for (int i : order)
+    if (sample_x(i)) items.push_back({i, 0, 0, 0});
+  add(p->sub, kXcore, 0, 0, b0);
 
   const int classes[4] = {16, 32, fm::kSmallLdsN, fm::kMaxN};
   // a sketch of a column class that fuses the Gram step leaves its partials
-  auto fused = [&](int i) {
-    return frames[i].method != FM_METHOD_SAMPLE && fm::sketch_fuses_gram(sketch_nb(frames[i].n));
-  };
+  auto fused = [&](int i) { return is_proj(i) && fm::sketch_fuses_gram(sketch_nb(frames[i].n)); };
   // after_sketch: this orth follows a product (round >= 1)
   auto orth_round = [&](auto pred, bool after_sketch) {
     size_t b = begin();
@@ -778,8 +848,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   };
   int qmax = 0;
   for (int i = 0; i < n_frames; ++i)
-    if (frames[i].method != FM_METHOD_SAMPLE) qmax = std::max(qmax, frames[i].q);
-  auto is_proj = [&](int i) { return frames[i].method != FM_METHOD_SAMPLE; };
+    if (is_proj(i)) qmax = std::max(qmax, frames[i].q);
   // round 0: orth(Omega) for q = 0 frames, then the first product for all
   orth_round([&](int i) { return is_proj(i) && frames[i].q == 0; }, false);
   sketch_round(is_proj, 0);

@@ -114,6 +114,15 @@ hipError_t launch_xhv(const FrameDev &single, const FrameDev *frames, const Item
 hipError_t launch_xz(const FrameDev &single, const FrameDev *frames, const Item *items,
                      int n_items, int nb, int round, hipStream_t s);
 constexpr int kXhvCols = 128;  // snapshots per xhv workgroup
+// Method 1 without forming R: launch_zx writes Z[t][j] = conj(X[idx_j][t])
+// (one workgroup per 64 snapshots), launch_xz (round < 0) forms
+// C = R(:, I) = X Z / T, launch_xcore takes core = C(I, :) and checks I
+// (one workgroup per frame).  p <= 64.
+hipError_t launch_zx(const FrameDev &single, const FrameDev *frames, const Item *items,
+                     int n_items, hipStream_t s);
+hipError_t launch_xcore(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, hipStream_t s);
+constexpr int kZxCols = 64;  // snapshots per zx workgroup
 hipError_t launch_gather(const FrameDev &single, const FrameDev *frames, const Item *items,
                          int n_items, hipStream_t s);
 hipError_t launch_gram(const FrameDev &single, const FrameDev *frames, const Item *items,

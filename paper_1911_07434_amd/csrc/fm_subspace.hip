@@ -409,6 +409,62 @@ __global__ __launch_bounds__(256) void xz_kernel(FrameDev single, const FrameDev
 }
 
 // ---------------------------------------------------------------------------
+// Method 1 without forming R: C = R(:, I) = X X(I, :)^H / T, core = C(I, :)
+// ---------------------------------------------------------------------------
+// Z[t][j] = conj(X[idx_j][t]) (the B operand of C = X Z / T), through an LDS
+// tile so that both the reads (along a row of X) and the writes (along j)
+// are contiguous.  Indices are clamped here and checked by xcore_kernel.
+template <bool kBatched>
+__global__ __launch_bounds__(256) void zx_kernel(FrameDev single, const FrameDev *frames,
+                                                 const Item *items) {
+  __shared__ float2 tile[kMaxL][kZxCols + 1];
+  int blk, unused;
+  const FrameDev &f = frame_of<kBatched>(single, frames, items, blk, unused);
+  const int p = f.n, M = f.M, T = f.T;
+  const int t0 = blk * kZxCols;
+  const int cols = min(T, t0 + kZxCols) - t0;
+  for (int e = threadIdx.x; e < p * kZxCols; e += blockDim.x) {
+    const int j = e / kZxCols, tt = e % kZxCols;
+    const int ij = min(max(f.idx[j], 0), M - 1);
+    float2 v = make_float2(0.f, 0.f);
+    if (tt < cols) v = f.X[(size_t)ij * f.ldx + t0 + tt];
+    tile[j][tt] = make_float2(v.x, -v.y);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < cols * p; e += blockDim.x) {
+    const int tt = e / p, j = e % p;
+    f.Z[(size_t)(t0 + tt) * p + j] = tile[j][tt];
+  }
+}
+
+// core = C(I, :) in FP64 (C = R(:, I) just formed in Y), the index check, and
+// the frame's status word
+template <bool kBatched>
+__global__ __launch_bounds__(256) void xcore_kernel(FrameDev single, const FrameDev *frames,
+                                                    const Item *items) {
+  __shared__ unsigned bad;
+  int unused_a, unused_b;
+  const FrameDev &f = frame_of<kBatched>(single, frames, items, unused_a, unused_b);
+  const int n = f.n, M = f.M, np = f.npad;
+  if (threadIdx.x == 0) bad = 0u;
+  __syncthreads();
+  double2 *core = slot(f, kSlotCore);
+  for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+    const int a = e / np, b = e % np;
+    double2 v = make_double2(0.0, 0.0);
+    if (a < n && b < n) {
+      const int ia = f.idx[a], ib = f.idx[b];
+      if (ia < 0 || ia >= M || (a != b && ia == ib)) atomicOr(&bad, (unsigned)FM_ST_BAD_INDEX);
+      const float2 c = f.Y[(size_t)min(max(ia, 0), M - 1) * n + b];
+      v = make_double2(c.x, c.y);
+    }
+    core[e] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *wstat_of(f) = bad;
+}
+
+// ---------------------------------------------------------------------------
 // gather (Method 1): C[m][j] = R[m][idx_j] = conj(R[idx_j][m]); chunk 0 also
 // forms core = R(I, I) in FP64 and checks the index set.
 // ---------------------------------------------------------------------------
@@ -507,7 +563,7 @@ __global__ __launch_bounds__(256) void gram_kernel(FrameDev single, const FrameD
   };
   if (mode == kGramSelf) {
     run(f.Y, f.Y, p0);
-  } else if (f.method != FM_METHOD_SAMPLE) {
+  } else if (f.method == FM_METHOD_PROJECT || f.method == FM_METHOD_PROJECT_X) {
     run(f.V, f.Y, p0);   // core = V^H (R V)
     run(f.Y, f.Y, p1);   // C^H C
   } else {
@@ -735,7 +791,7 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
   }
 
   // ---- final: core -> P, H = P^H Gc P -> W, sigma; T_f = P W_K sigma^-1/2 ----
-  const bool sample = f.method == FM_METHOD_SAMPLE;
+  const bool sample = f.method == FM_METHOD_SAMPLE || f.method == FM_METHOD_SAMPLE_X;
   // Gc (sum of partials, symmetrised) parked in its slot
   double2 *Gc = slot(f, kSlotGc);
   for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
@@ -952,6 +1008,22 @@ hipError_t launch_xz(const FrameDev &single, const FrameDev *frames, const Item 
     default: FM_XZ(4); break;
   }
 #undef FM_XZ
+  return hipGetLastError();
+}
+
+hipError_t launch_zx(const FrameDev &single, const FrameDev *frames, const Item *items,
+                     int n_items, hipStream_t s) {
+  const dim3 g(items ? n_items : (single.T + kZxCols - 1) / kZxCols), b(256);
+  if (items) hipLaunchKernelGGL(zx_kernel<true>, g, b, 0, s, single, frames, items);
+  else hipLaunchKernelGGL(zx_kernel<false>, g, b, 0, s, single, frames, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_xcore(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, hipStream_t s) {
+  const dim3 g(items ? n_items : 1), b(256);
+  if (items) hipLaunchKernelGGL(xcore_kernel<true>, g, b, 0, s, single, frames, items);
+  else hipLaunchKernelGGL(xcore_kernel<false>, g, b, 0, s, single, frames, items);
   return hipGetLastError();
 }
 

@@ -11,7 +11,9 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import (FM_FP16, FM_FP32, FM_METHOD_PROJECT, FM_METHOD_PROJECT_X, FM_METHOD_SAMPLE,
-               FM_RCOND_DEFAULT, fm_frame)
+               FM_METHOD_SAMPLE_X, FM_RCOND_DEFAULT, fm_frame)
+
+SAMPLE_METHODS = (FM_METHOD_SAMPLE, FM_METHOD_SAMPLE_X)
 
 
 @dataclass
@@ -37,7 +39,7 @@ class DeviceFrame:
         self.X = (torch.as_tensor(X).to(dev) if X is not None
                   else torch.empty((s.M, s.T), dtype=torch.complex64, device=dev))
         self.R = torch.empty((s.M, s.M), dtype=torch.complex64, device=dev)
-        if s.method != FM_METHOD_SAMPLE:
+        if s.method not in SAMPLE_METHODS:
             self.Omega = (torch.as_tensor(rnd).to(dev) if rnd is not None
                           else torch.empty((s.M, s.n), dtype=torch.float32, device=dev))
             self.idx = None
@@ -96,6 +98,8 @@ def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
         # Method 2 from the snapshots: no covariance (FP32 products)
         ctx.fm_subspace_project_x(fr.X, fr.Omega, s.q, s.K, fr.Us, fr.sigma, fr.status, s.rcond,
                                   FM_FP32, stream)
+    elif s.method == FM_METHOD_SAMPLE_X:
+        ctx.fm_subspace_sample_x(fr.X, fr.idx, s.K, fr.Us, fr.sigma, fr.status, s.rcond, stream)
     else:
         ctx.fm_covariance(fr.X, fr.R, prec, stream)
     if s.method == FM_METHOD_PROJECT:

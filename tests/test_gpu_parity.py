@@ -304,6 +304,39 @@ def test_subspace_from_x_matches_oracle(ctx, M, T, K, n, q):
         assert db_err(Pg, Po) <= DB_FP32
 
 
+@pytest.mark.parametrize("M,T,K,p", [(64, 128, 3, 44), (1024, 2048, 8, 64), (97, 50, 2, 9),
+                                     (130, 333, 6, 33), (200, 31, 4, 64), (65, 100, 1, 1)])
+def test_subspace_sample_from_x_matches_oracle(ctx, M, T, K, p):
+    say(f"Method 1 from X M={M} T={T} K={K} p={p}")
+    fr = fmsynth.make_frame(M, T, K, 10.0, seed=3 * M + T, angle_range=(-60, 60), min_sep=2)
+    idx = fmsynth.make_idx(M, p, M + p)
+    Us = torch.zeros((K, M), dtype=torch.complex128, device="cuda")
+    sig = torch.zeros(K, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.fm_subspace_sample_x(dev(fr.X), dev(idx), K, Us, sig, st)
+    torch.cuda.synchronize()
+    R = oracle.covariance(fr.X, threads=oracle.default_threads())
+    Uo, so, _ = oracle.subspace_sample(R, idx, K)
+    Ug, sg = Us.cpu().numpy(), sig.cpu().numpy()
+    d = np.linalg.norm(proj(Ug) - proj(Uo), 2)
+    say(f"  projector distance {d:.3g}, sigma rel {np.max(np.abs(sg - so) / so):.3g}")
+    assert int(st.cpu()[0]) == 0
+    assert d <= 1e-5
+    assert np.max(np.abs(sg - so) / so) <= 1e-5
+
+
+def test_subspace_sample_from_x_reports_bad_index(ctx):
+    M, T, K = 64, 96, 2
+    fr = fmsynth.make_frame(M, T, K, 10.0, seed=5)
+    Us = torch.zeros((K, M), dtype=torch.complex128, device="cuda")
+    sig = torch.zeros(K, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for bad in ([1, 5, 5, 9], [0, 3, 70, 2]):   # repeated, out of range
+        ctx.fm_subspace_sample_x(dev(fr.X), dev(np.array(bad, np.int32)), K, Us, sig, st)
+        torch.cuda.synchronize()
+        assert int(st.cpu()[0]) & fm.FM_ST_BAD_INDEX
+
+
 def test_subspace_from_x_validation(ctx):
     X = torch.zeros((16, 8), dtype=torch.complex64, device="cuda")
     Om = torch.zeros((16, 4), dtype=torch.float32, device="cuda")
@@ -316,6 +349,12 @@ def test_subspace_from_x_validation(ctx):
     with pytest.raises(fm.FmError) as e:
         ctx.fm_subspace_project_x(X, Om, 1, 5, Us, sig, st)          # K > l
     assert e.value.status == fm.FM_E_ARG
+    big = torch.arange(65, dtype=torch.int32, device="cuda") % 16
+    Xb = torch.zeros((128, 8), dtype=torch.complex64, device="cuda")
+    Ub = torch.zeros((2, 128), dtype=torch.complex128, device="cuda")
+    with pytest.raises(fm.FmError) as e:
+        ctx.fm_subspace_sample_x(Xb, big, 2, Ub, sig, st)            # p > 64
+    assert e.value.status == fm.FM_E_UNSUPPORTED
     small = fm.Context(0, 4096)
     with pytest.raises(fm.FmError) as e:
         small.fm_subspace_project_x(X, Om, 1, 2, Us, sig, st)       # arena too small
@@ -402,14 +441,17 @@ def _mixed_frames(n, seed):
         T = int(rng.integers(M // 2, 2 * M + 1))
         K = int(rng.integers(1, 9))
         l, p = fmsynth.sketch_sizes(M, K)
-        method = (fm.FM_METHOD_SAMPLE if i % 3 == 2 else
+        method = (fm.FM_METHOD_SAMPLE_X if i % 5 == 4 else
+                  fm.FM_METHOD_SAMPLE if i % 3 == 2 else
                   fm.FM_METHOD_PROJECT_X if i % 4 == 3 else fm.FM_METHOD_PROJECT)
-        n_ = p if method == fm.FM_METHOD_SAMPLE else l
+        sample = method in (fm.FM_METHOD_SAMPLE, fm.FM_METHOD_SAMPLE_X)
+        if method == fm.FM_METHOD_SAMPLE_X:
+            p = min(p, 64)
+        n_ = p if sample else l
         q = int(rng.integers(0, 3))
         L = int(rng.choice([181, 1801, 3001]))
         fr = fmsynth.make_frame(M, T, K, float(rng.uniform(-5, 20)), seed=seed * 1000 + i)
-        rnd = (fmsynth.make_idx(M, n_, i) if method == fm.FM_METHOD_SAMPLE
-               else fmsynth.make_omega(M, n_, i))
+        rnd = fmsynth.make_idx(M, n_, i) if sample else fmsynth.make_omega(M, n_, i)
         th0, dth, _ = fmsynth.grid(L)
         spec = FrameSpec(M=M, T=T, K=K, method=method, n=n_, q=q, L=L, theta0_deg=th0,
                          dtheta_deg=dth)
@@ -436,7 +478,7 @@ def test_batch_equals_alone_bitwise(ctx, use_graph):
         torch.cuda.synchronize()
         for a, d in zip(alone, devs):
             b = d.results()
-            if d.spec.method != fm.FM_METHOD_PROJECT_X:   # that method forms no R
+            if d.spec.method not in (fm.FM_METHOD_PROJECT_X, fm.FM_METHOD_SAMPLE_X):  # no R
                 assert np.array_equal(a["R"], b["R"])
             assert np.array_equal(a["Us"], b["Us"])
             assert np.array_equal(a["sigma"], b["sigma"])
@@ -568,7 +610,7 @@ def test_mixed_plan_equals_single_calls_bitwise(ctx):
         torch.cuda.synchronize()
         for a, d in zip(alone, devs):
             b = d.results()
-            if d.spec.method != fm.FM_METHOD_PROJECT_X:   # that method forms no R
+            if d.spec.method not in (fm.FM_METHOD_PROJECT_X, fm.FM_METHOD_SAMPLE_X):  # no R
                 assert np.array_equal(a["R"], b["R"])
             assert np.array_equal(a["P"], b["P"])
         plan.close()
