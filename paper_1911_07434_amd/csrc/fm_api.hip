@@ -725,7 +725,8 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     for (int i : order) {
       if (frames[i].method == FM_METHOD_PROJECT_X || frames[i].method == FM_METHOD_SAMPLE_X)
         continue;  // forms no R
-      const int nt = (frames[i].M + fm::kCovTile - 1) / fm::kCovTile;
+      const int e = fm::cov_edge(prec);
+      const int nt = (frames[i].M + e - 1) / e;
       if (ctx->knob[FM_KNOB_COV_SCHEDULE][cov_bucket(frames[i].M)] == 0) {
         // the whole frame onto the least-loaded XCD
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());

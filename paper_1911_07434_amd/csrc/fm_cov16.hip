@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256, 2) void cov16_kernel(FrameDev single,
 
 hipError_t launch_covariance16(const FrameDev &single, const FrameDev *frames, const Item *items,
                                int n_items, fm_prec prec, hipStream_t s) {
-  const dim3 g(items ? n_items : cov_tiles(single.M)), b(256);
+  const dim3 g(items ? n_items : cov_units(single.M, prec)), b(256);
   if (prec == FM_FP16) {
     if (items) hipLaunchKernelGGL((cov16_kernel<_Float16, true>), g, b, 0, s, single, frames, items);
     else hipLaunchKernelGGL((cov16_kernel<_Float16, false>), g, b, 0, s, single, frames, items);

@@ -63,7 +63,8 @@ struct Item {
 
 constexpr int kGramRows = 128;     // rows of the sketch per Gram partial
 constexpr int kSmallSlots = 8;     // npad^2 complex128 matrices per frame
-constexpr int kCovTile = 128;      // covariance tile edge (complex entries)
+constexpr int kCovTile = 128;      // 16-bit covariance: tile edge (complex entries)
+constexpr int kCovBlock = 64;      // FP32 covariance: block edge, one wave per block
 constexpr int kSketchRows = 128;   // rows of R per sketch workgroup
 constexpr int kApplyRows = 64;     // rows per apply / gather workgroup
 constexpr int kSpecChunk = 64;     // channels of U_s staged in LDS per step
@@ -152,9 +153,14 @@ hipError_t launch_refine(const FrameDev &single, const FrameDev *frames, const I
 hipError_t launch_peaks(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, hipStream_t s);
 
-// number of workgroups one frame needs in each stage (single-frame grids)
-inline int cov_tiles(int M) {
-  int nt = (M + kCovTile - 1) / kCovTile;
+// covariance work unit edge for a precision: the FP32 kernel runs one wave per
+// 64x64 block, the 16-bit kernel one workgroup per 128x128 tile
+inline int cov_edge(fm_prec prec) { return prec == FM_FP32 ? kCovBlock : kCovTile; }
+
+// number of covariance workgroups one frame needs (lower-triangle units)
+inline int cov_units(int M, fm_prec prec) {
+  const int e = cov_edge(prec);
+  const int nt = (M + e - 1) / e;
   return nt * (nt + 1) / 2;
 }
 
