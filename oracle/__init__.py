@@ -16,6 +16,9 @@ Automotive Massive-MIMO Radar", arXiv:1911.07434.
   - peaks               eq. (6)
   - Method 1            Alg. 1, eqs. (8)-(9), rank restriction of Sec. III-A
   - Method 2            Alg. 2, eq. (11)
+  - order of the model  Sec. V-D (AIC / MDL pre-estimation of K from the
+                        sketch eigenvalues; completion of the unseen
+                        eigenvalues from the trace is a reading)
 """
 from __future__ import annotations
 
@@ -74,6 +77,8 @@ def _load():
     lib.om_pseudospectrum.restype = None
     lib.om_peaks.argtypes = [P, C.c_int, C.c_int, P, P]
     lib.om_peaks.restype = C.c_int
+    lib.om_order.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, P]
+    lib.om_order.restype = C.c_int
     _lib = lib
     return lib
 
@@ -204,6 +209,31 @@ def peaks(P: np.ndarray, K: int):
     val = np.zeros(max(K, 1))
     n = _load().om_peaks(_p(P), L, K, _p(idx), _p(val))
     return idx[:n].copy(), val[:n].copy()
+
+
+ORDER_AIC, ORDER_MDL = 0, 1
+
+
+def order_criteria(sig, M: int, N: int, trR: float, kind: int, rcond: float = RCOND_DEFAULT):
+    """AIC (kind 0) / MDL (kind 1) over the sketch eigenvalues (Sec. V-D)
+    -> (K_hat, crit[n + 1]); crit is +inf where not evaluated."""
+    sig = np.ascontiguousarray(sig, dtype=np.float64)
+    n = sig.shape[0]
+    crit = np.zeros(n + 1)
+    k = _load().om_order(_p(sig), n, M, N, float(trR), rcond, kind, _p(crit))
+    return k, crit
+
+
+def order_estimate(R: np.ndarray, Omega: np.ndarray, q: int, N: int, kind: int,
+                   rcond: float = RCOND_DEFAULT):
+    """Pre-estimation of K (Sec. V-D): all l eigenvalues of the Method 2 sketch
+    of R, the trace of R, then the criterion -> (K_hat, crit, sig)."""
+    R = _c128(R)
+    l = np.asarray(Omega).shape[1]
+    _Us, sig, _ = subspace_project(R, Omega, q, l, rcond)
+    trR = float(np.sum(np.real(np.diag(R))))
+    k, crit = order_criteria(sig, R.shape[0], N, trR, kind, rcond)
+    return k, crit, sig
 
 
 # --------------------------------------------------------------------------

@@ -575,3 +575,55 @@ OM_EXPORT int om_peaks(const double *P, int L, int K, int32_t *idx, double *val)
   free(cand);
   return found;
 }
+
+/*
+ * Number of sources from the sketch eigenvalues (the pre-estimation of K that
+ * Sec. V-D proposes, with Akaike's information criterion or the minimum
+ * description length; both in their usual form for N snapshots of an
+ * M-channel array, where the noise eigenvalues lambda_{k+1..M} enter through
+ * the ratio of their arithmetic to their geometric mean):
+ *   L(k)   = N * ((M-k) * log(mean of noise) - sum of log(noise))      >= 0
+ *   AIC(k) = 2 L(k) + 2 k (2M - k)             (kind 0)
+ *   MDL(k) = L(k) + k (2M - k) log(N) / 2      (kind 1)
+ * Only the n eigenvalues of the Nystrom approximation are known (sig,
+ * descending).  Reading: those above rcond * sig[0] (and > 0) are kept, r of
+ * them; the other M - r eigenvalues of R are taken equal to their mean
+ * mu = (trR - sum of kept) / (M - r), which the exact trace of R fixes.
+ * k runs over 0..r (0..r-1 when r == M, where nothing is completed).
+ * crit[k] gets the criterion for k = 0..n (+INFINITY where not evaluated).
+ * Returns the first minimiser; returns r (crit all +INFINITY) when M > r and
+ * mu <= 0, i.e. the kept eigenvalues already hold the whole trace.
+ */
+OM_EXPORT int om_order(const double *sig, int n, int M, int N, double trR, double rcond,
+                       int kind, double *crit) {
+  for (int k = 0; k <= n; ++k) crit[k] = INFINITY;
+  int r = 0;
+  while (r < n && sig[r] > 0.0 && sig[r] > rcond * sig[0]) ++r;
+  double kept = 0.0;
+  for (int i = 0; i < r; ++i) kept += sig[i];
+  const int nc = M - r; /* completed eigenvalues */
+  double mu = 0.0;
+  if (nc > 0) {
+    mu = (trR - kept) / nc;
+    if (!(mu > 0.0)) return r;
+  }
+  const int kmax = nc > 0 ? r : r - 1;
+  int best = 0;
+  for (int k = 0; k <= kmax; ++k) {
+    double s = 0.0, ls = 0.0;
+    for (int i = k; i < r; ++i) {
+      s += sig[i];
+      ls += log(sig[i]);
+    }
+    if (nc > 0) {
+      s += nc * mu;
+      ls += nc * log(mu);
+    }
+    const int m = M - k;
+    const double Lk = (double)N * (m * log(s / m) - ls);
+    const double pen = (double)k * (2.0 * M - k);
+    crit[k] = kind == 0 ? 2.0 * Lk + 2.0 * pen : Lk + 0.5 * pen * log((double)N);
+    if (crit[k] < crit[best]) best = k;
+  }
+  return best;
+}
