@@ -103,6 +103,8 @@ typedef enum {
 #define FM_ST_RANK_DEFICIENT 8u  /* fewer than K non-zero directions survived */
 #define FM_ST_FEW_PEAKS     16u  /* fewer than K local maxima */
 #define FM_ST_BAD_INDEX     32u  /* sampled index outside [0, M) or repeated */
+#define FM_ST_ORDER_AT_LIMIT 64u  /* model-order estimate equals the sketch width
+                                    n: the sketch was too narrow to bound it */
 
 /* Default relative threshold of the eigen-based pseudo-inverse, eq. (8):
  * eigenvalues lambda <= rcond * lambda_max of the p x p (or l x l) core are
@@ -180,17 +182,6 @@ fm_status fm_subspace_project(fm_ctx *ctx, void *stream, const void *R, int M, i
                               const float *Omega, int l, int q, int K, double rcond,
                               fm_prec prec, void *Us, double *sigma, uint32_t *status);
 
-/* Method 2 straight from the snapshots: the same algorithm as
- * fm_subspace_project on R = X X^H / T (eqs. (2)-(3)), with every product
- * R V evaluated as X (X^H V) / T, so R is never formed -- identical in exact
- * arithmetic, (q+1) * 16 M T l real flops instead of 4 M^2 T for R, at the
- * cost of two reads of X per product.
- *   X      complex64 [M][ldx] snapshots (as fm_covariance)
- *   prec   FM_FP32 only (FM_E_UNSUPPORTED otherwise)
- *   other arguments as fm_subspace_project
- * Requires T >= 1, ldx >= T and the fm_subspace_project limits.  Uses
- * workspace: fm_workspace_bytes(M, l, K, 0) plus T * l * 8 bytes (rounded up
- * to 256). */
 /* Method 1 straight from the snapshots: the same algorithm as
  * fm_subspace_sample on R = X X^H / T, with the sampled columns formed as
  * C = R(:, I) = X X(I, :)^H / T and the core R(I, I) taken from C(I, :) --
@@ -203,10 +194,57 @@ fm_status fm_subspace_sample_x(fm_ctx *ctx, void *stream, const void *X, int M, 
                                int64_t ldx, const int32_t *idx, int p, int K, double rcond,
                                void *Us, double *sigma, uint32_t *status);
 
+/* Method 2 straight from the snapshots: the same algorithm as
+ * fm_subspace_project on R = X X^H / T (eqs. (2)-(3)), with every product
+ * R V evaluated as X (X^H V) / T, so R is never formed -- identical in exact
+ * arithmetic, (q+1) * 16 M T l real flops instead of 4 M^2 T for R, at the
+ * cost of two reads of X per product.
+ *   X      complex64 [M][ldx] snapshots (as fm_covariance)
+ *   prec   FM_FP32 only (FM_E_UNSUPPORTED otherwise)
+ *   other arguments as fm_subspace_project
+ * Requires T >= 1, ldx >= T and the fm_subspace_project limits.  Uses
+ * workspace: fm_workspace_bytes(M, l, K, 0) plus T * l * 8 bytes (rounded up
+ * to 256). */
 fm_status fm_subspace_project_x(fm_ctx *ctx, void *stream, const void *X, int M, int T,
                                 int64_t ldx, const float *Omega, int l, int q, int K,
                                 double rcond, fm_prec prec, void *Us, double *sigma,
                                 uint32_t *status);
+
+/* ------------------------------------------------------------------------ */
+/* model order: the number of sources when K is not known, Sec. V-D          */
+/* ------------------------------------------------------------------------ */
+
+/* Sec. V-D proposes estimating K before the fast method runs (with Akaike's
+ * information criterion or the minimum description length) and sizing the
+ * sketch from the estimate, p = ceil(1.2 K) in its Fig. 6. */
+typedef enum {
+  FM_ORDER_AIC = 0,  /* 2 L(k) + 2 k (2M - k) */
+  FM_ORDER_MDL = 1   /* L(k) + k (2M - k) log(N) / 2 */
+} fm_order_rule;
+
+/* K_hat = argmin over k of the criterion, where for N snapshots of M
+ * channels L(k) = N ((M-k) log(mean of noise) - sum of log(noise)) over the
+ * noise eigenvalues lambda_{k+1..M} of R.  Of those only the n eigenvalues
+ * of the Nystrom approximation are known (run fm_subspace_project, or
+ * fm_subspace_sample, with K = n: sigma then holds all n): the ones above
+ * rcond * eig[0] are used as they are (r of them) and the other M - r are
+ * taken equal to their mean (tr R - sum of kept) / (M - r), which the trace
+ * of R fixes; k runs over 0..r (0..r-1 when r == M).  If the kept
+ * eigenvalues already hold the whole trace (noiseless data), K_hat = r.
+ *   R       complex64 [M][ldr] (its diagonal gives the trace)
+ *   T       snapshots behind R (N of the criteria)
+ *   eig     double [n] (device): eigenvalues of S~, descending (0 past its
+ *           rank), e.g. the sigma of a subspace call with K = n
+ *   rule    fm_order_rule
+ *   K_hat   int32 [1] (device)
+ *   crit    double [n + 1] (device) criterion per k (+inf where not
+ *           evaluated), or null
+ *   status  uint32 [1] (device): FM_ST_ORDER_AT_LIMIT when K_hat == n
+ *           (overwritten)
+ * Requires M >= 2, T >= 1, 1 <= n <= min(M, 256).  No workspace. */
+fm_status fm_order(fm_ctx *ctx, void *stream, const void *R, int M, int64_t ldr, int T,
+                   const double *eig, int n, double rcond, int rule, int32_t *K_hat,
+                   double *crit, uint32_t *status);
 
 /* ------------------------------------------------------------------------ */
 /* stage 3: pseudo-spectrum, eqs. (5) and (10)                               */
@@ -269,6 +307,13 @@ typedef struct {
   int32_t *peak_idx;  /* int32 [K] */
   float *peak_val;    /* float32 [K] */
   int32_t *n_found;   /* int32 [1] */
+  /* model-order estimate (Sec. V-D), as fm_order, formed at the end of the
+   * subspace stage from all n eigenvalues of this frame's S~ and the trace
+   * of R; null: none.  Methods 1 and 2 on R only; its FM_ST_ORDER_AT_LIMIT
+   * bit is OR-ed into status. */
+  int32_t *K_hat;     /* int32 [1] */
+  double *order_crit; /* double [n + 1], or null */
+  int order_rule;     /* fm_order_rule */
 } fm_frame;
 
 /* Build a plan for n_frames frames (host array, copied): validates every

@@ -21,6 +21,8 @@ FM_FP32, FM_BF16, FM_FP16 = 0, 1, 2
 FM_METHOD_PROJECT, FM_METHOD_SAMPLE, FM_METHOD_PROJECT_X, FM_METHOD_SAMPLE_X = 0, 1, 2, 3
 FM_ST_NONFINITE, FM_ST_EIG_MAXIT, FM_ST_RANK_DEFICIENT, FM_ST_FEW_PEAKS, FM_ST_BAD_INDEX = (
     1, 4, 8, 16, 32)
+FM_ST_ORDER_AT_LIMIT = 64
+FM_ORDER_AIC, FM_ORDER_MDL = 0, 1
 FM_RCOND_DEFAULT = 1e-6
 FM_KNOB_COV_SCHEDULE, FM_KNOB_SPEC_ANGLES, FM_KNOB_SPEC16_ANGLES = 0, 1, 2
 
@@ -31,7 +33,7 @@ EXPORTS = (
     "fm_peaks", "fm_plan_create", "fm_plan_destroy", "fm_plan_workspace_bytes",
     "fm_plan_covariance", "fm_plan_subspace", "fm_plan_pseudospectrum", "fm_plan_peaks",
     "fm_plan_run", "fm_plan_bytes", "fm_plan_create_in", "fm_set_knob", "fm_get_knob",
-    "fm_subspace_project_x", "fm_subspace_sample_x",
+    "fm_subspace_project_x", "fm_subspace_sample_x", "fm_order",
 )
 
 
@@ -53,6 +55,7 @@ class fm_frame(C.Structure):
         ("L", C.c_int), ("theta0_deg", C.c_double), ("dtheta_deg", C.c_double),
         ("P", C.c_void_p), ("peak_idx", C.c_void_p), ("peak_val", C.c_void_p),
         ("n_found", C.c_void_p),
+        ("K_hat", C.c_void_p), ("order_crit", C.c_void_p), ("order_rule", C.c_int),
     ]
 
 
@@ -95,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "fm_subspace_project_x": ([P, P, P, I, I, I64, P, I, I, I, D, I, P, P, P], I),
         "fm_subspace_sample_x": ([P, P, P, I, I, I64, P, I, I, D, P, P, P], I),
         "fm_get_knob": ([P, I, I], I),
+        "fm_order": ([P, P, P, I, I64, I, P, I, D, I, P, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -185,6 +189,13 @@ class Context:
         self.check(self.lib.fm_subspace_sample_x(self.h, _stream(stream), _ptr(X), M, T,
                                                  X.stride(0), _ptr(idx), idx.shape[0], K, rcond,
                                                  _ptr(Us), _ptr(sigma), _ptr(status)))
+
+    def fm_order(self, R, T, eig, K_hat, status, rule=FM_ORDER_MDL, crit=None,
+                 rcond=FM_RCOND_DEFAULT, stream=None):
+        M = R.shape[0]
+        self.check(self.lib.fm_order(self.h, _stream(stream), _ptr(R), M, R.stride(0), T,
+                                     _ptr(eig), eig.shape[0], rcond, rule, _ptr(K_hat),
+                                     _ptr(crit), _ptr(status)))
 
     def fm_pseudospectrum(self, Us, theta0_deg, dtheta_deg, L, P, prec=FM_FP32, stream=None):
         K, M = Us.shape

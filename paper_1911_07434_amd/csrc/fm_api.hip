@@ -85,7 +85,7 @@ namespace {
 
 enum Kind { kCov, kOmega, kGather, kSketch, kSketch16, kXhv, kXz, kZx, kXcore, kGram, kSmall, kApply,
              kSpecPrep, kSpec, kSplit, kSpec16, kRefine,
-            kPeaks };
+            kPeaks, kOrder };
 
 fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
   if (ctx) {
@@ -107,7 +107,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // per-frame workspace layout (shared by single-frame calls and plans)
 struct WsLayout {
-  size_t y, v, z, part, small, uf, rlist, total;
+  size_t y, v, z, part, small, uf, rlist, eig, total;
   bool has_z;
 };
 
@@ -125,6 +125,7 @@ WsLayout ws_layout(int M, int n, int K, int L, int Tz = 0) {
   w.small = o; o += align256(((size_t)fm::kSmallSlots * np * np + 1) * 16);
   w.uf = o;    o += align256((size_t)M * K * 8);
   w.rlist = o; o += align256((size_t)(L + 1) * 4);
+  w.eig = o;   o += align256((size_t)n * 8);
   w.total = o;
   return w;
 }
@@ -137,6 +138,7 @@ void bind_ws(FrameDev &f, char *base, const WsLayout &w) {
   f.small = reinterpret_cast<double2 *>(base + w.small);
   f.Uf = reinterpret_cast<float2 *>(base + w.uf);
   f.rlist = reinterpret_cast<int *>(base + w.rlist);
+  f.eig = reinterpret_cast<double *>(base + w.eig);
   f.nchunk = (f.M + fm::kGramRows - 1) / fm::kGramRows;
   f.npad = (f.n + 1) & ~1;
 }
@@ -497,6 +499,37 @@ FM_API fm_status fm_subspace_project(fm_ctx *ctx, void *stream, const void *R, i
                          Us, sigma, status);
 }
 
+FM_API fm_status fm_order(fm_ctx *ctx, void *stream, const void *R, int M, int64_t ldr, int T,
+                          const double *eig, int n, double rcond, int rule, int32_t *K_hat,
+                          double *crit, uint32_t *status) {
+  if (!ctx) return FM_E_ARG;
+  if (!R || !eig || !K_hat || !status) return fail(ctx, FM_E_ARG, "order: null pointer");
+  if (M < 2 || T < 1) return fail(ctx, FM_E_ARG, "order: need M >= 2 and T >= 1 (M=%d T=%d)", M, T);
+  if (ldr < M) return fail(ctx, FM_E_ARG, "order: ldr (%lld) < M (%d)", (long long)ldr, M);
+  if (n < 1 || n > M || n > fm::kMaxN)
+    return fail(ctx, FM_E_ARG, "order: need 1 <= n <= min(M, %d) (n=%d M=%d)", fm::kMaxN, n, M);
+  if (rule != FM_ORDER_AIC && rule != FM_ORDER_MDL)
+    return fail(ctx, FM_E_ARG, "order: unknown rule %d", rule);
+  if (!(rcond >= 0.0) || !std::isfinite(rcond)) return fail(ctx, FM_E_ARG, "order: bad rcond");
+  fm_status st = set_dev(ctx);
+  if (st != FM_OK) return st;
+  FrameDev f = blank_frame();
+  f.R = static_cast<float2 *>(const_cast<void *>(R));
+  f.ldr = ldr;
+  f.M = M;
+  f.T = T;
+  f.n = n;
+  f.rcond = rcond;
+  f.eig = const_cast<double *>(eig);
+  f.K_hat = K_hat;
+  f.order_crit = crit;
+  f.order_rule = rule;
+  f.order_or_status = 0;
+  f.status = status;
+  FM_CHECK_LAUNCH(ctx, fm::launch_order(f, nullptr, nullptr, 0, (hipStream_t)stream));
+  return FM_OK;
+}
+
 FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, int M, int K,
                                    double theta0_deg, double dtheta_deg, int L, fm_prec prec,
                                    float *P) {
@@ -584,6 +617,7 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kSpec16: return fm::launch_spectrum16(cls, fr, it, L.count, L.n_class, L.mode, s);
     case kRefine: return fm::launch_refine(cls, fr, it, L.count, s);
     case kPeaks: return fm::launch_peaks(cls, fr, it, L.count, s);
+    case kOrder: return fm::launch_order(cls, fr, it, L.count, s);
   }
   return hipErrorInvalidValue;
 }
@@ -623,6 +657,13 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
                      a.Us, a.sigma, a.status);
     if (st == FM_OK) st = check_spec(ctx, a.Us, a.M, a.K, a.theta0_deg, a.dtheta_deg, a.L, a.P);
     if (st == FM_OK) st = check_peaks(ctx, a.P, a.L, a.K, a.peak_idx, a.peak_val, a.n_found);
+    if (st == FM_OK && a.K_hat) {
+      if (from_x)
+        st = fail(ctx, FM_E_ARG, "model order: needs R (Method 1 or 2 on R, method %d)",
+                  a.method);
+      else if (a.order_rule != FM_ORDER_AIC && a.order_rule != FM_ORDER_MDL)
+        st = fail(ctx, FM_E_ARG, "model order: unknown rule %d", a.order_rule);
+    }
     if (st != FM_OK) {
       std::string m = ctx->err;
       return fail(ctx, st, "plan frame %d: %s", i, m.c_str());
@@ -689,6 +730,10 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     f.peak_idx = a.peak_idx;
     f.peak_val = a.peak_val;
     f.n_found = a.n_found;
+    f.K_hat = a.K_hat;
+    f.order_crit = a.order_crit;
+    f.order_rule = a.order_rule;
+    f.order_or_status = 1;
     bind_ws(f, p->ws + off[i], lay[i]);
     p->frames_h[i] = f;
   }
@@ -873,6 +918,11 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   for (int i : order)
     for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
   add(p->sub, kApply, fm::kApplyUs, 0, b0);
+  // model order of the frames that ask for it (after the status words are set)
+  b0 = begin();
+  for (int i : order)
+    if (frames[i].K_hat) items.push_back({i, 0, 0, 0});
+  add(p->sub, kOrder, 0, 0, b0);
 
   if (prec == FM_FP32) {
     b0 = begin();

@@ -52,6 +52,12 @@ struct FrameDev {
   float2 *Uf;           // FP32 pass: [M][K] FP32 copy of U_s; FP16 pass: scaled
                         // hi and lo planes [K][M] of (re, im) FP16 pairs
   int *rlist;           // [1 + L]: count, then angles whose FP32 denominator needs FP64
+  double *eig;          // [n]: every eigenvalue of S~ (descending, 0 past its rank)
+  // model-order estimate (Sec. V-D); K_hat == null: none
+  int *K_hat;           // [1]
+  double *order_crit;   // [n + 1] criterion values, or null
+  int order_rule;       // FM_ORDER_AIC / FM_ORDER_MDL
+  int order_or_status;  // 1: OR the order bits into *status (plans), 0: overwrite
   int nchunk;           // ceil(M / kGramRows)
   int npad;             // n rounded up to even
 };
@@ -124,6 +130,10 @@ hipError_t launch_zx(const FrameDev &single, const FrameDev *frames, const Item 
 hipError_t launch_xcore(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, hipStream_t s);
 constexpr int kZxCols = 64;  // snapshots per zx workgroup
+// model order from the eigenvalues f.eig and the trace of f.R (one
+// workgroup per frame)
+hipError_t launch_order(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, hipStream_t s);
 hipError_t launch_gather(const FrameDev &single, const FrameDev *frames, const Item *items,
                          int n_items, hipStream_t s);
 hipError_t launch_gram(const FrameDev &single, const FrameDev *frames, const Item *items,

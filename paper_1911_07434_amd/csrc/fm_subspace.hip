@@ -886,6 +886,10 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
     Tf[e] = acc;
   }
   __syncthreads();
+  // every eigenvalue of S~, for the model-order estimate
+  if (f.eig)
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+      f.eig[k] = (k < r1 && S.w[k] > 0.0) ? S.w[k] : 0.0;
   if (threadIdx.x == 0) {
     unsigned st = S.st | *wstat_of(f);
     for (int k = 0; k < K; ++k) {

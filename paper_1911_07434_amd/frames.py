@@ -28,6 +28,7 @@ class FrameSpec:
     theta0_deg: float = -90.0
     dtheta_deg: float = 0.01
     rcond: float = FM_RCOND_DEFAULT
+    order_rule: int | None = None  # FM_ORDER_AIC / FM_ORDER_MDL: also estimate K (Sec. V-D)
 
 
 class DeviceFrame:
@@ -54,6 +55,11 @@ class DeviceFrame:
         self.peak_idx = torch.zeros((s.K,), dtype=torch.int32, device=dev)
         self.peak_val = torch.zeros((s.K,), dtype=torch.float32, device=dev)
         self.n_found = torch.zeros((1,), dtype=torch.int32, device=dev)
+        if s.order_rule is not None:
+            self.K_hat = torch.full((1,), -1, dtype=torch.int32, device=dev)
+            self.order_crit = torch.zeros((s.n + 1,), dtype=torch.float64, device=dev)
+        else:
+            self.K_hat = self.order_crit = None
 
     def descriptor(self) -> fm_frame:
         s = self.spec
@@ -76,15 +82,23 @@ class DeviceFrame:
         f.peak_idx = self.peak_idx.data_ptr()
         f.peak_val = self.peak_val.data_ptr()
         f.n_found = self.n_found.data_ptr()
+        if s.order_rule is not None:
+            f.K_hat = self.K_hat.data_ptr()
+            f.order_crit = self.order_crit.data_ptr()
+            f.order_rule = s.order_rule
         return f
 
     def results(self) -> dict:
         """Copy the outputs back to host numpy arrays."""
         nf = int(self.n_found.cpu()[0])
-        return dict(R=self.R.cpu().numpy(), Us=self.Us.cpu().numpy(),
-                    sigma=self.sigma.cpu().numpy(), status=int(self.status.cpu()[0]),
-                    P=self.P.cpu().numpy(), peak_idx=self.peak_idx.cpu().numpy()[:nf],
-                    peak_val=self.peak_val.cpu().numpy()[:nf], n_found=nf)
+        out = dict(R=self.R.cpu().numpy(), Us=self.Us.cpu().numpy(),
+                   sigma=self.sigma.cpu().numpy(), status=int(self.status.cpu()[0]),
+                   P=self.P.cpu().numpy(), peak_idx=self.peak_idx.cpu().numpy()[:nf],
+                   peak_val=self.peak_val.cpu().numpy()[:nf], n_found=nf)
+        if self.K_hat is not None:
+            out["K_hat"] = int(self.K_hat.cpu()[0])
+            out["order_crit"] = self.order_crit.cpu().numpy()
+        return out
 
 
 def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
@@ -110,3 +124,37 @@ def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
     sprec = FM_FP32 if prec == FM_FP32 else FM_FP16
     ctx.fm_pseudospectrum(fr.Us, s.theta0_deg, s.dtheta_deg, s.L, fr.P, sprec, stream)
     ctx.fm_peaks(fr.P, s.K, fr.peak_idx, fr.peak_val, fr.n_found, stream)
+
+
+def sampling_length(K_hat: int, M: int, factor: float = 1.2) -> int:
+    """Method 1's sampling length from an estimated number of sources: the
+    over-estimate p = ceil(1.2 K_hat) of Sec. V-D (Fig. 6), at least 1, at
+    most M."""
+    import math
+    return max(1, min(M, math.ceil(factor * K_hat - 1e-9)))
+
+
+def estimate_order_single(ctx, fr: DeviceFrame, rule: int, prec=FM_FP32, stream=None):
+    """Model order of one frame through the single-frame entry points (the
+    pre-estimation of Sec. V-D): covariance, the frame's sketch with every
+    direction kept (its K must equal n, so sigma holds all n eigenvalues),
+    then fm_order.  Writes fr.K_hat (and fr.order_crit)."""
+    import torch
+    s = fr.spec
+    if s.K != s.n:
+        raise ValueError("order estimate needs the sketch with every direction kept (K == n)")
+    if fr.K_hat is None:
+        fr.K_hat = torch.full((1,), -1, dtype=torch.int32, device=fr.X.device)
+        fr.order_crit = torch.zeros((s.n + 1,), dtype=torch.float64, device=fr.X.device)
+    ctx.fm_covariance(fr.X, fr.R, prec, stream)
+    if s.method == FM_METHOD_PROJECT:
+        ctx.fm_subspace_project(fr.R, fr.Omega, s.q, s.K, fr.Us, fr.sigma, fr.status, s.rcond,
+                                prec, stream)
+    elif s.method == FM_METHOD_SAMPLE:
+        ctx.fm_subspace_sample(fr.R, fr.idx, s.K, fr.Us, fr.sigma, fr.status, s.rcond, stream)
+    else:
+        raise ValueError("order estimate needs R (Method 1 or 2 on R)")
+    ord_status = torch.zeros((1,), dtype=torch.int32, device=fr.X.device)
+    ctx.fm_order(fr.R, s.T, fr.sigma, fr.K_hat, ord_status,
+                 rule if rule is not None else s.order_rule, fr.order_crit, s.rcond, stream)
+    return ord_status
