@@ -394,10 +394,10 @@ def main():
             del planm
         out["mixed_precision"] = mixed
         out["mixed_precision_note"] = ("covariance operands in FP16/BF16 with FP32 "
-                                       "accumulation; sketch FP32; spectrum on FP16 matrix "
-                                       "cores with hi+lo split operands (three products, FP32 "
-                                       "accumulation); small dense steps and peak-region "
-                                       "denominators FP64")
+                                       "accumulation; Method 2 sketch on FP16 matrix cores "
+                                       "with hi+lo split operands (three products, FP32 "
+                                       "accumulation); spectrum FP32 (polynomial pass); small "
+                                       "dense steps and peak-region denominators FP64")
 
         # ---- Method 1 on the same frames -----------------------------------
         del plan2

@@ -65,11 +65,13 @@ typedef enum {
  * every mode.
  *   covariance (fm_covariance, stage 1 of a plan): operands rounded to the
  *     given precision.
- *   pseudo-spectrum (fm_pseudospectrum, stage 3 of a plan): FM_FP32 uses FP32
- *     products; FM_FP16 splits U_s and the steering twiddles into FP16 hi + lo
- *     halves and accumulates hi*hi + hi*lo + lo*hi (~22-bit products).
- *     fm_pseudospectrum rejects FM_BF16 (FM_E_UNSUPPORTED); a plan at either
- *     16-bit precision runs the FP16 split spectrum.
+ *   pseudo-spectrum (fm_pseudospectrum): FM_FP32 evaluates the spectrum as a
+ *     polynomial in sin(theta) on FP32 products (one length-M product per
+ *     angle, see fm_pseudospectrum); FM_FP16 splits U_s and the steering
+ *     twiddles into FP16 hi + lo halves and accumulates hi*hi + hi*lo +
+ *     lo*hi (~22-bit products), K products per angle.  fm_pseudospectrum
+ *     rejects FM_BF16 (FM_E_UNSUPPORTED).  Plans at every precision run the
+ *     FP32 polynomial pass (faster and more accurate than the FP16 one).
  *   sketch products Y = R V (fm_subspace_project, stage 2 of a plan):
  *     FM_FP32 uses FP32 products; FM_FP16 and FM_BF16 split R and V into
  *     FP16 hi + lo halves (power-of-two scaled) and accumulate hi*hi + hi*lo
@@ -250,9 +252,12 @@ fm_status fm_order(fm_ctx *ctx, void *stream, const void *R, int M, int64_t ldr,
 /* stage 3: pseudo-spectrum, eqs. (5) and (10)                               */
 /* ------------------------------------------------------------------------ */
 
-/* P_l = 1 / (M - ||U_s^H a(theta_l)||^2) on the grid theta_l.  The bulk of
- * the grid is evaluated with FP32 products (prec FM_FP32) or compensated
- * FP16 hi + lo products (prec FM_FP16); every point whose denominator falls
+/* P_l = 1 / (M - ||U_s^H a(theta_l)||^2) on the grid theta_l.  With FM_FP32
+ * the bulk of the grid is evaluated through the identity
+ * ||U_s^H a||^2 = 2 Re sum_d h'_d a_d(theta), h'_d the lag sums of U_s U_s^H
+ * along its d-th diagonal (h'_0 halved): one length-M product per angle on
+ * FP32 matrix cores, whatever K is; with FM_FP16 through the K products
+ * c_k = u_k^H a with compensated FP16 hi + lo operands.  Every point whose denominator falls
  * below M/16 -- the cancellation-prone region around peaks -- is recomputed
  * in FP64.  A denominator below M*2^-53 is
  * clamped there (the pole of a noiseless on-grid source).
@@ -322,8 +327,7 @@ typedef struct {
  * frame is computed exactly as the single-frame entry points compute it:
  * fm_covariance and fm_subspace_project at the plan's precision `prec`,
  * fm_subspace_sample at FM_FP32,
- * fm_pseudospectrum at FM_FP32 for an FP32 plan and at FM_FP16 for a 16-bit
- * plan. */
+ * fm_pseudospectrum at FM_FP32 for every plan. */
 fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,
                          fm_plan **out);
 /* Device bytes a plan for these frames needs (workspace, descriptors and

@@ -14,8 +14,9 @@ Knobs and buckets:
   cov_schedule   bucket log2(M) - 7 in [0, 5]; 0 = a frame's covariance tiles
                  on one XCD, 1 = tiles dealt one by one to the XCDs
   spec_angles    bucket ceil(K/8) - 1 in [0, 7]; angles per workgroup of the
-                 FP32 spectrum pass (64, 128, 256 for buckets 0..3)
-  spec16_angles  the same for the compensated FP16 pass
+                 FP32 (polynomial) spectrum pass, which every plan runs (64,
+                 128, 256 for buckets 0..3)
+  spec16_angles  the same for the compensated FP16 pass (single-frame calls)
 """
 from __future__ import annotations
 
@@ -57,9 +58,10 @@ def choices(knob: int, bucket: int) -> list[int]:
 
 
 def knobs_for(prec: int) -> list[int]:
-    """Knobs that affect a plan at precision `prec`."""
-    spec = FM_KNOB_SPEC_ANGLES if prec == FM_FP32 else FM_KNOB_SPEC16_ANGLES
-    return [FM_KNOB_COV_SCHEDULE, spec]
+    """Knobs that affect a plan at precision `prec` (every plan runs the FP32
+    polynomial spectrum pass; the FP16 pass knob only affects single-frame
+    fm_pseudospectrum calls at FM_FP16)."""
+    return [FM_KNOB_COV_SCHEDULE, FM_KNOB_SPEC_ANGLES]
 
 
 @dataclass

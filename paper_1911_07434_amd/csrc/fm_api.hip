@@ -5,7 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -84,8 +86,7 @@ struct fm_plan {
 namespace {
 
 enum Kind { kCov, kOmega, kGather, kSketch, kSketch16, kXhv, kXz, kZx, kXcore, kGram, kSmall, kApply,
-             kSpecPrep, kSpec, kSplit, kSpec16, kRefine,
-            kPeaks, kOrder };
+             kSpecPrep, kRefine, kPeaks, kOrder, kAcorr, kPoly };
 
 fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
   if (ctx) {
@@ -540,7 +541,9 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
   if (prec == FM_BF16)
     return fail(ctx, FM_E_UNSUPPORTED, "pseudospectrum: FM_FP32 or FM_FP16 (compensated) only");
   const size_t uf_bytes = align256((size_t)M * K * 8);
-  const size_t need = uf_bytes + align256((size_t)(L + 1) * 4);
+  const size_t rl_bytes = align256((size_t)(L + 1) * 4);
+  const size_t need = uf_bytes + rl_bytes +
+                      (prec == FM_FP32 ? align256((size_t)M * fm::kPolyRows * 8) : 0);
   if (need > ctx->arena_bytes)
     return fail(ctx, FM_E_WORKSPACE, "pseudospectrum: needs %zu arena bytes", need);
   if ((st = set_dev(ctx)) != FM_OK) return st;
@@ -557,9 +560,14 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
   hipStream_t s = (hipStream_t)stream;
   const int nb = spec_nb(K);
   if (prec == FM_FP32) {
+    // a group of one: lag sums, then the polynomial pass
     const int nnb = ctx->knob[FM_KNOB_SPEC_ANGLES][nb - 1] / 64;
+    f.hgrp = reinterpret_cast<float2 *>(ctx->arena + uf_bytes + rl_bytes);
+    f.hslot = 0;
+    f.hcount = 1;
     FM_CHECK_LAUNCH(ctx, fm::launch_uf(f, s));
-    FM_CHECK_LAUNCH(ctx, fm::launch_spectrum(f, nullptr, nullptr, 0, nb, nnb, s));
+    FM_CHECK_LAUNCH(ctx, fm::launch_acorr(f, nullptr, nullptr, 0, s));
+    FM_CHECK_LAUNCH(ctx, fm::launch_poly(f, nullptr, nullptr, 0, nnb, s));
   } else {
     const int nnb = ctx->knob[FM_KNOB_SPEC16_ANGLES][nb - 1] / 64;
     FM_CHECK_LAUNCH(ctx, fm::launch_split(f, nullptr, nullptr, 0, s));
@@ -612,12 +620,11 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kSmall: return fm::launch_small(cls, fr, it, L.count, L.mode, s);
     case kApply: return fm::launch_apply(cls, fr, it, L.count, L.mode, s);
     case kSpecPrep: return fm::launch_spec_prep(fr, it, L.count, s);
-    case kSpec: return fm::launch_spectrum(cls, fr, it, L.count, L.n_class, L.mode, s);
-    case kSplit: return fm::launch_split(cls, fr, it, L.count, s);
-    case kSpec16: return fm::launch_spectrum16(cls, fr, it, L.count, L.n_class, L.mode, s);
     case kRefine: return fm::launch_refine(cls, fr, it, L.count, s);
     case kPeaks: return fm::launch_peaks(cls, fr, it, L.count, s);
     case kOrder: return fm::launch_order(cls, fr, it, L.count, s);
+    case kAcorr: return fm::launch_acorr(cls, fr, it, L.count, s);
+    case kPoly: return fm::launch_poly(cls, fr, it, L.count, L.mode, s);
   }
   return hipErrorInvalidValue;
 }
@@ -690,6 +697,34 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     off[i] = total;
     total += lay[i].total;
   }
+  // spectrum groups (every plan runs the FP32 polynomial pass): frames with equal M, angle grid and spectrum knob
+  // bucket, up to kPolyRows per group (in frame order), each with a group
+  // buffer [M][kPolyRows] placed after the frames' workspaces
+  std::vector<int> grp_of(n_frames, -1), slot_of(n_frames, 0);
+  std::vector<std::vector<int>> groups;
+  std::vector<size_t> goff;
+  {
+    std::map<std::tuple<int, int, uint64_t, uint64_t, int>, int> open;
+    for (int i = 0; i < n_frames; ++i) {
+      uint64_t t0, dt;
+      std::memcpy(&t0, &frames[i].theta0_deg, 8);
+      std::memcpy(&dt, &frames[i].dtheta_deg, 8);
+      const auto key = std::make_tuple(frames[i].M, frames[i].L, t0, dt, spec_nb(frames[i].K));
+      auto it = open.find(key);
+      if (it == open.end() || (int)groups[it->second].size() == fm::kPolyRows) {
+        groups.emplace_back();
+        open[key] = (int)groups.size() - 1;
+      }
+      const int g = open[key];
+      slot_of[i] = (int)groups[g].size();
+      grp_of[i] = g;
+      groups[g].push_back(i);
+    }
+    for (const auto &g : groups) {
+      goff.push_back(total);
+      total += align256((size_t)frames[g[0]].M * fm::kPolyRows * 8);
+    }
+  }
   p->ws_bytes = total;
   hipError_t e = hipSuccess;
   if (dry_run) {
@@ -735,6 +770,11 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     f.order_rule = a.order_rule;
     f.order_or_status = 1;
     bind_ws(f, p->ws + off[i], lay[i]);
+    if (grp_of[i] >= 0) {
+      f.hgrp = reinterpret_cast<float2 *>(p->ws + goff[grp_of[i]]);
+      f.hslot = slot_of[i];
+      f.hcount = (int)groups[grp_of[i]].size();
+    }
     p->frames_h[i] = f;
   }
 
@@ -924,26 +964,24 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     if (frames[i].K_hat) items.push_back({i, 0, 0, 0});
   add(p->sub, kOrder, 0, 0, b0);
 
-  if (prec == FM_FP32) {
+  // spectrum (every precision): reset the recompute lists, lag sums of
+  // every frame into its group buffer, then each group's polynomial pass
+  // (tiles of the knob's width for the group's bucket)
+  b0 = begin();
+  for (int i : order) items.push_back({i, 0, 0, 0});
+  add(p->spec, kSpecPrep, 0, 0, b0);
+  b0 = begin();
+  for (int i : order)
+    for (int c = 0; c < rows(frames[i].M, fm::kAcorrLags); ++c) items.push_back({i, c, 0, 0});
+  add(p->spec, kAcorr, 0, 0, b0);
+  for (int per : {256, 128, 64}) {
     b0 = begin();
-    for (int i : order) items.push_back({i, 0, 0, 0});
-    add(p->spec, kSpecPrep, 0, 0, b0);
-  } else {
-    b0 = begin();
-    for (int i : order)
-      for (int t = 0; t < rows(frames[i].K * frames[i].M, 256); ++t) items.push_back({i, t, 0, 0});
-    add(p->spec, kSplit, 0, 0, b0);
-  }
-  {
-    const int knob = prec == FM_FP32 ? FM_KNOB_SPEC_ANGLES : FM_KNOB_SPEC16_ANGLES;
-    for (int nb = 1; nb <= 8; ++nb) {
-      const int per = ctx->knob[knob][nb - 1];
-      b0 = begin();
-      for (int i : order)
-        if (spec_nb(frames[i].K) == nb)
-          for (int t = 0; t < rows(frames[i].L, per); ++t) items.push_back({i, t, 0, 0});
-      add(p->spec, prec == FM_FP32 ? kSpec : kSpec16, per / 64, nb, b0);
+    for (const auto &g : groups) {
+      const int lead = g[0];
+      if (ctx->knob[FM_KNOB_SPEC_ANGLES][spec_nb(frames[lead].K) - 1] != per) continue;
+      for (int t = 0; t < rows(frames[lead].L, per); ++t) items.push_back({lead, t, 0, 0});
     }
+    add(p->spec, kPoly, per / 64, 0, b0);
   }
   b0 = begin();
   for (int i : order)
@@ -953,6 +991,17 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   for (int i : order) items.push_back({i, 0, 0, 0});
   add(p->peaks, kPeaks, 0, 0, b0);
 
+  // member lists of the spectrum groups (16 frame indices, -1 padded) ride
+  // at the end of the work-list upload
+  std::vector<size_t> gitem(groups.size());
+  for (size_t g = 0; g < groups.size(); ++g) {
+    gitem[g] = items.size();
+    int mem[fm::kPolyRows];
+    for (int j = 0; j < fm::kPolyRows; ++j)
+      mem[j] = j < (int)groups[g].size() ? groups[g][j] : -1;
+    static_assert(fm::kPolyRows % 4 == 0, "member list packs into whole items");
+    for (int j = 0; j < fm::kPolyRows; j += 4) items.push_back({mem[j], mem[j + 1], mem[j + 2], mem[j + 3]});
+  }
   p->items_bytes = items.size() * sizeof(Item);
   const size_t frames_bytes = align256(sizeof(FrameDev) * n_frames);
   const size_t total_dev = total + frames_bytes + align256(std::max<size_t>(p->items_bytes, 16));
@@ -962,8 +1011,15 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     return FM_OK;
   }
   p->items_h = std::move(items);
+  // the member lists' device address, once the work lists have one
+  auto bind_members = [&]() {
+    for (int i = 0; i < n_frames; ++i)
+      if (grp_of[i] >= 0)
+        p->frames_h[i].hmem = reinterpret_cast<const int *>(p->items_d + gitem[grp_of[i]]);
+  };
   if (p->owned) {
     e = hipMalloc((void **)&p->items_d, std::max<size_t>(p->items_bytes, 256));
+    if (e == hipSuccess) bind_members();
     if (e == hipSuccess) e = hipMalloc((void **)&p->frames_d, sizeof(FrameDev) * n_frames);
     if (e == hipSuccess)
       e = hipMemcpy(p->items_d, p->items_h.data(), p->items_bytes, hipMemcpyHostToDevice);
@@ -979,6 +1035,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     }
     p->frames_d = reinterpret_cast<FrameDev *>(dev + total);
     p->items_d = reinterpret_cast<Item *>(dev + total + frames_bytes);
+    bind_members();
     e = hipMemcpyAsync(p->items_d, p->items_h.data(), p->items_bytes, hipMemcpyHostToDevice,
                        stream);
     if (e == hipSuccess)

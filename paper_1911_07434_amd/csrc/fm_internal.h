@@ -53,6 +53,12 @@ struct FrameDev {
                         // hi and lo planes [K][M] of (re, im) FP16 pairs
   int *rlist;           // [1 + L]: count, then angles whose FP32 denominator needs FP64
   double *eig;          // [n]: every eigenvalue of S~ (descending, 0 past its rank)
+  // FP32 spectrum as a polynomial in sin(theta): frames of equal M and grid
+  // share a group buffer hgrp [M][kPolyRows] (column hslot: this frame's
+  // conj(h'_d)); hmem lists the group's frames (plan indices), hcount of them
+  float2 *hgrp;
+  const int *hmem;
+  int hslot, hcount;
   // model-order estimate (Sec. V-D); K_hat == null: none
   int *K_hat;           // [1]
   double *order_crit;   // [n + 1] criterion values, or null
@@ -73,7 +79,9 @@ constexpr int kCovTile = 128;      // 16-bit covariance: tile edge (complex entr
 constexpr int kCovBlock = 64;      // FP32 covariance: block edge, one wave per block
 constexpr int kSketchRows = 128;   // rows of R per sketch workgroup
 constexpr int kApplyRows = 64;     // rows per apply / gather workgroup
-constexpr int kSpecChunk = 64;     // channels of U_s staged in LDS per step
+constexpr int kSpecChunk = 64;     // lags staged in LDS per step of the polynomial pass
+constexpr int kPolyRows = 16;      // frames per polynomial-spectrum group (MFMA rows)
+constexpr int kAcorrLags = 256;    // lags d per autocorrelation workgroup
 constexpr int kRefineGroups = 4;   // FP64 recompute workgroups per frame
 constexpr int kMaxL = 64;          // max sketch width of Method 2 (l)
 constexpr int kMaxN = 256;         // max sketch width of Method 1 (p)
@@ -144,13 +152,11 @@ hipError_t launch_apply(const FrameDev &single, const FrameDev *frames, const It
                         int n_items, int mode, hipStream_t s);
 hipError_t launch_uf(const FrameDev &single, hipStream_t s);
 // spectrum stage = prep (reset the recompute lists; batched only -- the
-// single-frame path resets it in launch_uf), the FP32 pass (one launch per
-// row-block class nb = ceil(K / 8); tiles of 64 nnb angles, nnb in {1, 2}
-// and also 4 for nb <= 4) and the FP64 recompute of the listed angles
+// single-frame path resets it in launch_uf), a bulk pass (the FP32
+// polynomial pass of fm_poly.hip, or the compensated FP16 pass) and the
+// FP64 recompute of the listed angles
 hipError_t launch_spec_prep(const FrameDev *frames, const Item *items, int n_items,
                             hipStream_t s);
-hipError_t launch_spectrum(const FrameDev &single, const FrameDev *frames, const Item *items,
-                           int n_items, int nb, int nnb, hipStream_t s);
 // compensated FP16 pass: launch_split writes the hi and lo planes of U_s
 // (one workgroup per 256 entries; resets the recompute list), then one
 // spectrum16 launch per class nb = ceil(K / 8) over tiles of 64 nnb angles
@@ -158,6 +164,15 @@ hipError_t launch_split(const FrameDev &single, const FrameDev *frames, const It
                         int n_items, hipStream_t s);
 hipError_t launch_spectrum16(const FrameDev &single, const FrameDev *frames, const Item *items,
                              int n_items, int nb, int nnb, hipStream_t s);
+// FP32 spectrum as a polynomial in u = sin(theta): launch_acorr writes each
+// frame's lag sums h'_d into its group buffer (one workgroup per 256 lags;
+// needs Uf and resets nothing), launch_poly evaluates a group of up to 16
+// frames over tiles of 64 nnb angles (nnb in {1, 2, 4}); items name the
+// group's first frame
+hipError_t launch_acorr(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, hipStream_t s);
+hipError_t launch_poly(const FrameDev &single, const FrameDev *frames, const Item *items,
+                       int n_items, int nnb, hipStream_t s);
 hipError_t launch_refine(const FrameDev &single, const FrameDev *frames, const Item *items,
                          int n_items, hipStream_t s);
 hipError_t launch_peaks(const FrameDev &single, const FrameDev *frames, const Item *items,

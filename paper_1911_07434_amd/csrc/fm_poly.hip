@@ -1,0 +1,230 @@
+// fm_poly.hip -- stage 3, FP32 bulk pass: the MUSIC pseudo-spectrum
+// (eqs. (5) and (10)) evaluated as a trigonometric polynomial in sin(theta).
+//
+// With c_k = sum_m conj(U[k][m]) a_m and a_m = exp(-j pi m u), u = sin(theta),
+//   sum_k |c_k|^2 = sum_{m,m'} Q[m][m'] a_m conj(a_m'),  Q[m][m'] = sum_k conj(U[k][m]) U[k][m'],
+// and a_m conj(a_m') = a_{m-m'} depends on the lag d = m - m' only, so
+//   sum_k |c_k|^2 = h_0 + 2 Re sum_{d>=1} h_d a_d,  h_d = sum_k sum_m' conj(U[k][m'+d]) U[k][m']
+// (h_{-d} = conj(h_d)).  With h'_0 = h_0 / 2 and h'_d = h_d otherwise,
+//   den(theta) = M - 2 Re sum_{d=0}^{M-1} h'_d a_d(theta),   P = 1 / den:
+// one length-M inner product per angle whatever K is, against the steering
+// vector itself.  This is the same quantity as eq. (5) in exact arithmetic.
+//
+// acorr: the lag sums h'_d of one frame in FP32 from the FP32 copy Uf of U_s
+//   (one thread per lag, the frame's columns staged through LDS; fixed
+//   summation order over k, then m).
+// poly:  frames with the same M and angle grid form groups of up to 16; the
+//   group's conj(h') vectors are the 16 rows of v_mfma_f32_16x16x4_f32 and the
+//   angles its columns, so each generated steering phasor and each staged
+//   operand serve the whole group.  A frame's rows of the products do not
+//   depend on the other rows, so a frame's result is the same in any group
+//   (or alone).  Steering, the FP32 floor and the list of main-lobe angles
+//   for the FP64 recompute are those of the per-frame pass.
+#include "fm_internal.h"
+#include "fm_steer.h"
+
+namespace fm {
+namespace {
+
+using namespace steer;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kAcM = 1024;  // rows of a column staged per acorr step
+
+template <bool kBatched>
+__global__ __launch_bounds__(256) void acorr_kernel(FrameDev single, const FrameDev *frames,
+                                                    const Item *items) {
+  __shared__ float2 wa[kAcM];
+  __shared__ float2 wb[kAcM + kAcorrLags];
+  int chunk;
+  const FrameDev *fp;
+  if constexpr (kBatched) {
+    const Item it = items[blockIdx.x];
+    chunk = it.a;
+    fp = frames + it.frame;
+  } else {
+    chunk = blockIdx.x;
+    fp = &single;
+  }
+  const int M = fp->M, K = fp->K;
+  const float2 *Uf = fp->Uf;
+  float2 *hg = fp->hgrp;
+  const int slot = fp->hslot;
+  const int tid = threadIdx.x;
+  const int d0 = chunk * kAcorrLags, d = d0 + tid;
+  float re = 0.f, im = 0.f;
+  for (int k = 0; k < K; ++k) {
+    for (int m0 = 0; m0 < M - d0; m0 += kAcM) {
+      __syncthreads();  // the previous window has been read
+      for (int i = tid; i < kAcM; i += 256)
+        wa[i] = (m0 + i < M) ? Uf[(size_t)(m0 + i) * K + k] : make_float2(0.f, 0.f);
+      for (int i = tid; i < kAcM + kAcorrLags; i += 256)
+        wb[i] = (m0 + d0 + i < M) ? Uf[(size_t)(m0 + d0 + i) * K + k] : make_float2(0.f, 0.f);
+      __syncthreads();
+      const int cnt = min(kAcM, M - d - m0);  // lags past M - 1 - m contribute nothing
+      for (int i = 0; i < cnt; ++i) {
+        // conj(U[k][m + d]) * U[k][m], m = m0 + i
+        const float2 x = wb[i + tid], y = wa[i];
+        re = fmaf(x.x, y.x, fmaf(x.y, y.y, re));
+        im = fmaf(x.x, y.y, fmaf(-x.y, y.x, im));
+      }
+    }
+  }
+  if (d < M) {
+    if (d == 0) {
+      re *= 0.5f;  // h'_0 = h_0 / 2 (h_0 is real)
+      im = 0.f;
+    }
+    hg[(size_t)d * kPolyRows + slot] = make_float2(re, -im);  // conj(h'_d)
+  }
+}
+
+// one tile of 64 NNB angles of a group (four waves of 16 NNB angles); the
+// group buffer is staged through LDS in chunks of kSpecChunk lags, double
+// buffered like the per-frame pass
+template <int NNB, bool kBatched>
+__device__ __forceinline__ void poly_tile(const FrameDev &single, const FrameDev *frames,
+                                          const FrameDev &g, int tile, const float2 *tab,
+                                          float2 (*hbuf)[kSpecChunk * kPolyRows]) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int n = lane & 15, r = lane >> 4;
+  const int M = g.M, L = g.L;
+  const float2 *hg = g.hgrp;
+  const int first = tile * (64 * NNB) + wave * (16 * NNB);
+  unsigned long long F[NNB];
+#pragma unroll
+  for (int nb = 0; nb < NNB; ++nb)
+    F[nb] = turn_freq(g.theta0, g.dtheta, min(first + 16 * nb + n, L - 1));
+  floatx4 acc[NNB];
+#pragma unroll
+  for (int nb = 0; nb < NNB; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  constexpr int kChunkElems = kSpecChunk * kPolyRows;  // 1024 float2, 4 per thread
+  const int nchunk = (M + kSpecChunk - 1) / kSpecChunk;
+  const size_t total = (size_t)M * kPolyRows;
+  float2 stage[kChunkElems / 256];
+  auto load_chunk = [&](int c) {
+    const size_t base = (size_t)c * kChunkElems;
+#pragma unroll
+    for (int j = 0; j < kChunkElems / 256; ++j) {
+      const size_t e = base + tid + 256 * j;
+      stage[j] = e < total ? hg[e] : make_float2(0.f, 0.f);
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < kChunkElems / 256; ++j) hbuf[buf][tid + 256 * j] = stage[j];
+  };
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();  // publishes the first chunk and the phasor table
+  float2 w4[NNB], ph[NNB];
+#pragma unroll
+  for (int nb = 0; nb < NNB; ++nb) w4[nb] = phasor32(4u, F[nb], tab);
+
+  for (int c = 0; c < nchunk; ++c) {
+    const bool more = c + 1 < nchunk;
+    if (more) load_chunk(c + 1);
+    const float2 *hb = hbuf[c & 1];
+#pragma unroll 4
+    for (int s = 0; s < kSpecChunk / 4; ++s) {
+      const int d = c * kSpecChunk + 4 * s + r;
+#pragma unroll
+      for (int nb = 0; nb < NNB; ++nb)
+        ph[nb] = (s == 0) ? phasor32((unsigned)d, F[nb], tab) : cmulf(ph[nb], w4[nb]);
+      // row n = group slot n: u = conj(h'_d), Re(conj(u) a) = u.x a.x + u.y a.y
+      const float2 u = hb[(4 * s + r) * kPolyRows + n];
+#pragma unroll
+      for (int nb = 0; nb < NNB; ++nb) {
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(u.x, ph[nb].x, acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(u.y, ph[nb].y, acc[nb], 0, 0, 0);
+      }
+    }
+    if (more) store_chunk((c + 1) & 1);
+    __syncthreads();
+  }
+  // lane (r, n) holds rows 4r..4r+3 (group slots) of angle column n
+  const float Mf = (float)M;
+  const float floor32 = Mf * 5.9604644775390625e-08f;  // M * 2^-24
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int slot = 4 * r + v;
+    if (slot >= g.hcount) continue;
+    const FrameDev &f = kBatched ? frames[g.hmem[slot]] : single;
+    float *P = f.P;
+    int *rlist = f.rlist;
+#pragma unroll
+    for (int nb = 0; nb < NNB; ++nb) {
+      const int gl = first + 16 * nb + n;
+      if (gl < L) {
+        const float den32 = fmaf(-2.0f, acc[nb][v], Mf);
+        P[gl] = 1.0f / fmaxf(den32, floor32);
+        // main lobes, where the denominator cancels, are recomputed in FP64
+        if (den32 < Mf * 0.0625f) {
+          const int k = atomicAdd(rlist, 1);
+          rlist[1 + k] = gl;
+        }
+      }
+    }
+  }
+}
+
+template <int NNB, bool kBatched>
+__global__ __launch_bounds__(256) void poly_kernel(FrameDev single, const FrameDev *frames,
+                                                   const Item *items) {
+  __shared__ float2 tab[256];
+  __shared__ float2 hbuf[2][kSpecChunk * kPolyRows];
+  {
+    double s, c;
+    sincospi((double)threadIdx.x / 128.0, &s, &c);
+    tab[threadIdx.x] = make_float2((float)c, (float)s);
+  }
+  // (the first __syncthreads in poly_tile also publishes the table)
+  if constexpr (kBatched) {
+    const Item it = items[blockIdx.x];
+    poly_tile<NNB, true>(single, frames, frames[it.frame], it.a, tab, hbuf);
+  } else {
+    poly_tile<NNB, false>(single, frames, single, blockIdx.x, tab, hbuf);
+  }
+}
+
+template <int NNB>
+hipError_t launch_poly_nnb(const FrameDev &single, const FrameDev *frames, const Item *items,
+                           int n_items, hipStream_t s) {
+  if (items) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL((poly_kernel<NNB, true>), dim3(n_items), dim3(256), 0, s, single, frames,
+                       items);
+  } else {
+    const int tiles = (single.L + 64 * NNB - 1) / (64 * NNB);
+    hipLaunchKernelGGL((poly_kernel<NNB, false>), dim3(tiles), dim3(256), 0, s, single, frames,
+                       items);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_acorr(const FrameDev &single, const FrameDev *frames, const Item *items,
+                        int n_items, hipStream_t s) {
+  if (items) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(acorr_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames, items);
+  } else {
+    const int chunks = (single.M + kAcorrLags - 1) / kAcorrLags;
+    hipLaunchKernelGGL(acorr_kernel<false>, dim3(chunks), dim3(256), 0, s, single, frames, items);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_poly(const FrameDev &single, const FrameDev *frames, const Item *items,
+                       int n_items, int nnb, hipStream_t s) {
+  if (nnb == 4) return launch_poly_nnb<4>(single, frames, items, n_items, s);
+  if (nnb == 2) return launch_poly_nnb<2>(single, frames, items, n_items, s);
+  return launch_poly_nnb<1>(single, frames, items, n_items, s);
+}
+
+}  // namespace fm

@@ -10,7 +10,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (FM_FP16, FM_FP32, FM_METHOD_PROJECT, FM_METHOD_PROJECT_X, FM_METHOD_SAMPLE,
+from . import (FM_FP32, FM_METHOD_PROJECT, FM_METHOD_PROJECT_X, FM_METHOD_SAMPLE,
                FM_METHOD_SAMPLE_X, FM_RCOND_DEFAULT, fm_frame)
 
 SAMPLE_METHODS = (FM_METHOD_SAMPLE, FM_METHOD_SAMPLE_X)
@@ -105,8 +105,7 @@ def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
     """All four stages of one frame through the single-frame entry points, as
     a plan at precision `prec` runs them: the covariance and the Method 2
     sketch at `prec`, Method 1 and Method 2 from X (no covariance) in FP32,
-    the spectrum in FP32 (FP32 plan) or with compensated FP16 products
-    (16-bit plan)."""
+    the spectrum in FP32 (the polynomial pass every plan runs)."""
     s = fr.spec
     if s.method == FM_METHOD_PROJECT_X:
         # Method 2 from the snapshots: no covariance (FP32 products)
@@ -121,8 +120,7 @@ def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
                                 prec, stream)
     elif s.method == FM_METHOD_SAMPLE:
         ctx.fm_subspace_sample(fr.R, fr.idx, s.K, fr.Us, fr.sigma, fr.status, s.rcond, stream)
-    sprec = FM_FP32 if prec == FM_FP32 else FM_FP16
-    ctx.fm_pseudospectrum(fr.Us, s.theta0_deg, s.dtheta_deg, s.L, fr.P, sprec, stream)
+    ctx.fm_pseudospectrum(fr.Us, s.theta0_deg, s.dtheta_deg, s.L, fr.P, FM_FP32, stream)
     ctx.fm_peaks(fr.P, s.K, fr.peak_idx, fr.peak_val, fr.n_found, stream)
 
 

@@ -50,7 +50,8 @@ def test_buckets_and_choices():
     assert at.choices(fm.FM_KNOB_SPEC_ANGLES, 3) == [64, 128, 256]
     assert at.choices(fm.FM_KNOB_SPEC16_ANGLES, 4) == [64, 128]
     assert at.knobs_for(fm.FM_FP32) == [fm.FM_KNOB_COV_SCHEDULE, fm.FM_KNOB_SPEC_ANGLES]
-    assert at.knobs_for(fm.FM_FP16) == [fm.FM_KNOB_COV_SCHEDULE, fm.FM_KNOB_SPEC16_ANGLES]
+    # every plan runs the FP32 polynomial spectrum pass
+    assert at.knobs_for(fm.FM_FP16) == [fm.FM_KNOB_COV_SCHEDULE, fm.FM_KNOB_SPEC_ANGLES]
 
 
 def test_tune_picks_fastest_variant_per_bucket_and_installs_it():
@@ -94,7 +95,7 @@ def test_tune_ties_go_to_the_smaller_value_and_max_frames_caps_the_sample():
         return 2.0
     table = at.tune(ctx, frames, fm.FM_FP16, max_frames=4, make_plan=FakePlan, time_stage=flat)
     assert table[fm.FM_KNOB_COV_SCHEDULE][2].value == 0
-    assert table[fm.FM_KNOB_SPEC16_ANGLES][0].value == 64
+    assert table[fm.FM_KNOB_SPEC_ANGLES][0].value == 64
     assert set(seen) == {4}
 
 

@@ -93,7 +93,7 @@ def test_every_variant_bitwise_identical(ctx, prec):
     frames = _uneven(16, seed=71)
     say(f"variants prec={prec}: K = {sorted(s.K for s, _, _ in frames)}")
     ref = _run(ctx, frames, prec)
-    spec_knob = fm.FM_KNOB_SPEC_ANGLES if prec == fm.FM_FP32 else fm.FM_KNOB_SPEC16_ANGLES
+    spec_knob = fm.FM_KNOB_SPEC_ANGLES  # every plan runs the FP32 polynomial spectrum pass
     for v in (1, 0):
         for b in range(6):
             ctx.set_knob(fm.FM_KNOB_COV_SCHEDULE, b, v)
