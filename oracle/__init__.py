@@ -16,6 +16,8 @@ Automotive Massive-MIMO Radar", arXiv:1911.07434.
   - peaks               eq. (6)
   - Method 1            Alg. 1, eqs. (8)-(9), rank restriction of Sec. III-A
   - Method 2            Alg. 2, eq. (11)
+  - ESPRIT on U_s      the conclusion's extension to other subspace
+                        estimators (least-squares ESPRIT: a reading)
   - order of the model  Sec. V-D (AIC / MDL pre-estimation of K from the
                         sketch eigenvalues; completion of the unseen
                         eigenvalues from the trace is a reading)
@@ -79,6 +81,10 @@ def _load():
     lib.om_peaks.restype = C.c_int
     lib.om_order.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, P]
     lib.om_order.restype = C.c_int
+    lib.om_eigvals.argtypes = [P, C.c_int, P]
+    lib.om_eigvals.restype = C.c_int
+    lib.om_esprit.argtypes = [P, C.c_int, C.c_int, P]
+    lib.om_esprit.restype = C.c_int
     _lib = lib
     return lib
 
@@ -234,6 +240,24 @@ def order_estimate(R: np.ndarray, Omega: np.ndarray, q: int, N: int, kind: int,
     trR = float(np.sum(np.real(np.diag(R))))
     k, crit = order_criteria(sig, R.shape[0], N, trR, kind, rcond)
     return k, crit, sig
+
+
+def eigvals(A: np.ndarray):
+    """Eigenvalues of a general complex matrix (Hessenberg + shifted QR) -> (w, steps)."""
+    A = _c128(A)
+    n = A.shape[0]
+    w = np.zeros(n, np.complex128)
+    st = _load().om_eigvals(_p(A), n, _p(w))
+    return w, st
+
+
+def esprit(Us: np.ndarray):
+    """Least-squares ESPRIT on U_s [K][M] -> (angles in degrees ascending, steps)."""
+    Us = _c128(Us)
+    K, M = Us.shape
+    doa = np.zeros(K)
+    st = _load().om_esprit(_p(Us), M, K, _p(doa))
+    return doa, st
 
 
 # --------------------------------------------------------------------------

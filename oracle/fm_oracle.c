@@ -627,3 +627,184 @@ OM_EXPORT int om_order(const double *sig, int n, int M, int N, double trR, doubl
   }
   return best;
 }
+
+/*
+ * Eigenvalues of a general complex n x n matrix: Householder reduction to
+ * upper Hessenberg form, then implicitly shifted QR (one complex Wilkinson
+ * shift per step from the trailing 2x2 of the active block, Givens bulge
+ * chase, deflation where a subdiagonal falls below eps * the neighbouring
+ * diagonal).  Eigenvalues only.  A is overwritten.  Returns the number of
+ * QR steps, or -1 past 30 n steps.
+ */
+static int hessenberg_qr(zc *A, int n, zc *w) {
+  for (int c = 0; c + 2 < n; ++c) {
+    const int len = n - c - 1;
+    zc *v = zalloc(len);
+    double nx = 0;
+    for (int i = 0; i < len; ++i) {
+      v[i] = A[(size_t)(c + 1 + i) * n + c];
+      nx += zabs2(v[i]);
+    }
+    nx = sqrt(nx);
+    if (nx > 0) {
+      const double a0 = cabs(v[0]);
+      const zc ph = a0 > 0 ? v[0] / a0 : 1.0;
+      v[0] += ph * nx; /* v = x + sign(x0) |x| e_0 */
+      double nv = 0;
+      for (int i = 0; i < len; ++i) nv += zabs2(v[i]);
+      nv = sqrt(nv);
+      for (int i = 0; i < len; ++i) v[i] /= nv;
+      /* A <- (I - 2 v v^H) A on rows c+1.. */
+      for (int j = 0; j < n; ++j) {
+        zc s = 0;
+        for (int i = 0; i < len; ++i) s += conj(v[i]) * A[(size_t)(c + 1 + i) * n + j];
+        for (int i = 0; i < len; ++i) A[(size_t)(c + 1 + i) * n + j] -= 2.0 * v[i] * s;
+      }
+      /* A <- A (I - 2 v v^H) on columns c+1.. */
+      for (int i = 0; i < n; ++i) {
+        zc s = 0;
+        for (int j = 0; j < len; ++j) s += A[(size_t)i * n + c + 1 + j] * v[j];
+        for (int j = 0; j < len; ++j) A[(size_t)i * n + c + 1 + j] -= 2.0 * s * conj(v[j]);
+      }
+    }
+    free(v);
+  }
+  int steps = 0, hi = n - 1;
+  const double eps = 2.220446049250313e-16;
+  while (hi >= 0) {
+    if (hi == 0) {
+      w[0] = A[0];
+      break;
+    }
+    int l = hi;
+    while (l > 0) {
+      const double sub = cabs(A[(size_t)l * n + l - 1]);
+      double ref = cabs(A[(size_t)l * n + l]) + cabs(A[(size_t)(l - 1) * n + l - 1]);
+      if (ref == 0) ref = 1.0;
+      if (sub <= eps * ref) break;
+      --l;
+    }
+    if (l == hi) { /* 1 x 1 block converged */
+      w[hi] = A[(size_t)hi * n + hi];
+      --hi;
+      continue;
+    }
+    if (++steps > 30 * n) return -1;
+    /* Wilkinson shift: the eigenvalue of the trailing 2x2 nearer to its last entry */
+    const zc a = A[(size_t)(hi - 1) * n + hi - 1], b = A[(size_t)(hi - 1) * n + hi];
+    const zc cc = A[(size_t)hi * n + hi - 1], d = A[(size_t)hi * n + hi];
+    const zc tr2 = 0.5 * (a + d), det = a * d - b * cc;
+    const zc disc = csqrt(tr2 * tr2 - det);
+    const zc e1 = tr2 + disc, e2 = tr2 - disc;
+    zc mu = cabs(e1 - d) <= cabs(e2 - d) ? e1 : e2;
+    if (steps % 11 == 0) mu = d + cabs(cc); /* exceptional shift against stagnation */
+    zc x = A[(size_t)l * n + l] - mu, y = A[(size_t)(l + 1) * n + l];
+    for (int k = l; k < hi; ++k) {
+      if (k > l) {
+        x = A[(size_t)k * n + k - 1];
+        y = A[(size_t)(k + 1) * n + k - 1];
+      }
+      const double ax = cabs(x), rho = sqrt(ax * ax + zabs2(y));
+      if (rho == 0) continue;
+      double gc;
+      zc gs;
+      if (ax == 0) {
+        gc = 0;
+        gs = conj(y) / cabs(y);
+      } else {
+        gc = ax / rho;
+        gs = (x / ax) * conj(y) / rho;
+      }
+      /* rows k, k+1: [c s; -conj(s) c] */
+      for (int j = (k > l ? k - 1 : l); j <= hi; ++j) {
+        const zc p = A[(size_t)k * n + j], q = A[(size_t)(k + 1) * n + j];
+        A[(size_t)k * n + j] = gc * p + gs * q;
+        A[(size_t)(k + 1) * n + j] = -conj(gs) * p + gc * q;
+      }
+      /* columns k, k+1: times the conjugate transpose */
+      const int iend = k + 2 < hi ? k + 2 : hi;
+      for (int i = l; i <= iend; ++i) {
+        const zc p = A[(size_t)i * n + k], q = A[(size_t)i * n + k + 1];
+        A[(size_t)i * n + k] = gc * p + conj(gs) * q;
+        A[(size_t)i * n + k + 1] = -gs * p + gc * q;
+      }
+    }
+  }
+  return steps;
+}
+
+/* Eigenvalues of a general complex matrix (for pinning hessenberg_qr). */
+OM_EXPORT int om_eigvals(const double *A, int n, double *w) {
+  zc *T = zalloc((size_t)n * n);
+  memcpy(T, A, sizeof(zc) * (size_t)n * n);
+  int r = hessenberg_qr(T, n, (zc *)w);
+  free(T);
+  return r;
+}
+
+/*
+ * ESPRIT on a signal subspace (the extension of the fast subspace to other
+ * estimators that the conclusion proposes; reading: least-squares ESPRIT on
+ * the two maximally overlapping subarrays of the ULA).  With U1 = rows
+ * 0..M-2 and U2 = rows 1..M-1 of U_s (M x K), Psi = (U1^H U1)^-1 U1^H U2
+ * (Gaussian elimination with partial pivoting); its eigenvalues are
+ * exp(-j pi sin(theta_k)) for a_m = exp(-j pi m sin(theta)), so
+ * theta_k = asin(-arg(phi_k) / pi).  Us is [K][M] column-contiguous.
+ * doa_deg gets the K angles in degrees, ascending.  Returns the QR step
+ * count, or -1 if the eigenvalue iteration did not converge.
+ */
+OM_EXPORT int om_esprit(const double *Us, int M, int K, double *doa_deg) {
+  const zc *U = (const zc *)Us;
+  zc *Aug = zalloc((size_t)K * 2 * K);
+  for (int a = 0; a < K; ++a)
+    for (int b = 0; b < K; ++b) {
+      zc g = 0, h = 0;
+      for (int m = 0; m + 1 < M; ++m) {
+        g += conj(U[(size_t)a * M + m]) * U[(size_t)b * M + m];
+        h += conj(U[(size_t)a * M + m]) * U[(size_t)b * M + m + 1];
+      }
+      Aug[(size_t)a * 2 * K + b] = g;
+      Aug[(size_t)a * 2 * K + K + b] = h;
+    }
+  /* [G | H] -> [I | G^-1 H] */
+  for (int c = 0; c < K; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < K; ++r)
+      if (cabs(Aug[(size_t)r * 2 * K + c]) > cabs(Aug[(size_t)piv * 2 * K + c])) piv = r;
+    if (piv != c)
+      for (int j = 0; j < 2 * K; ++j) {
+        const zc t = Aug[(size_t)c * 2 * K + j];
+        Aug[(size_t)c * 2 * K + j] = Aug[(size_t)piv * 2 * K + j];
+        Aug[(size_t)piv * 2 * K + j] = t;
+      }
+    const zc p = Aug[(size_t)c * 2 * K + c];
+    for (int j = 0; j < 2 * K; ++j) Aug[(size_t)c * 2 * K + j] /= p;
+    for (int r = 0; r < K; ++r) {
+      if (r == c) continue;
+      const zc f = Aug[(size_t)r * 2 * K + c];
+      for (int j = 0; j < 2 * K; ++j) Aug[(size_t)r * 2 * K + j] -= f * Aug[(size_t)c * 2 * K + j];
+    }
+  }
+  zc *Psi = zalloc((size_t)K * K), *w = zalloc(K);
+  for (int a = 0; a < K; ++a)
+    for (int b = 0; b < K; ++b) Psi[(size_t)a * K + b] = Aug[(size_t)a * 2 * K + K + b];
+  const int st = hessenberg_qr(Psi, K, w);
+  for (int k = 0; k < K; ++k) {
+    double u = -carg(w[k]) / 3.141592653589793;
+    if (u > 1) u = 1;
+    if (u < -1) u = -1;
+    doa_deg[k] = asin(u) * (180.0 / 3.141592653589793);
+  }
+  /* ascending (insertion sort) */
+  for (int i = 1; i < K; ++i) {
+    const double t = doa_deg[i];
+    int j = i - 1;
+    while (j >= 0 && doa_deg[j] > t) {
+      doa_deg[j + 1] = doa_deg[j];
+      --j;
+    }
+    doa_deg[j + 1] = t;
+  }
+  free(Aug); free(Psi); free(w);
+  return st;
+}
