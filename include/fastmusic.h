@@ -249,6 +249,25 @@ fm_status fm_order(fm_ctx *ctx, void *stream, const void *R, int M, int64_t ldr,
                    double *crit, uint32_t *status);
 
 /* ------------------------------------------------------------------------ */
+/* ESPRIT on the fast subspace (the conclusion's extension, Sec. VI)        */
+/* ------------------------------------------------------------------------ */
+
+/* Angles of the K sources from a signal subspace by least-squares ESPRIT on
+ * the two shifted subarrays of the ULA: with U1 = rows 0..M-2 and U2 = rows
+ * 1..M-1 of U_s, Psi = (U1^H U1)^-1 U1^H U2 and its eigenvalues are
+ * exp(-j pi sin(theta_k)) for the steering of fm_pseudospectrum, so
+ * theta_k = asin(-arg(phi_k) / pi).  Computed in FP64 (Gauss-Jordan with
+ * partial pivoting, Householder Hessenberg reduction, shifted QR) by one
+ * workgroup; no spectrum and no peak search.
+ *   Us       complex128 [K][M] orthonormal columns (stage 2 output)
+ *   doa_deg  double [K] (device): the angles in degrees, ascending
+ *   status   uint32 [1] (device): FM_ST_EIG_MAXIT if the QR iteration hit
+ *            its step limit (overwritten)
+ * Requires 1 <= K < M, K <= 32.  No workspace. */
+fm_status fm_esprit(fm_ctx *ctx, void *stream, const void *Us, int M, int K, double *doa_deg,
+                    uint32_t *status);
+
+/* ------------------------------------------------------------------------ */
 /* stage 3: pseudo-spectrum, eqs. (5) and (10)                               */
 /* ------------------------------------------------------------------------ */
 
@@ -319,6 +338,10 @@ typedef struct {
   int32_t *K_hat;     /* int32 [1] */
   double *order_crit; /* double [n + 1], or null */
   int order_rule;     /* fm_order_rule */
+  /* ESPRIT angles of this frame's U_s, as fm_esprit, formed at the end of
+   * the subspace stage (K <= 32); null: none.  FM_ST_EIG_MAXIT is OR-ed
+   * into status. */
+  double *esprit_deg; /* double [K] */
 } fm_frame;
 
 /* Build a plan for n_frames frames (host array, copied): validates every

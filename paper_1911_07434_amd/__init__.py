@@ -33,7 +33,7 @@ EXPORTS = (
     "fm_peaks", "fm_plan_create", "fm_plan_destroy", "fm_plan_workspace_bytes",
     "fm_plan_covariance", "fm_plan_subspace", "fm_plan_pseudospectrum", "fm_plan_peaks",
     "fm_plan_run", "fm_plan_bytes", "fm_plan_create_in", "fm_set_knob", "fm_get_knob",
-    "fm_subspace_project_x", "fm_subspace_sample_x", "fm_order",
+    "fm_subspace_project_x", "fm_subspace_sample_x", "fm_order", "fm_esprit",
 )
 
 
@@ -56,6 +56,7 @@ class fm_frame(C.Structure):
         ("P", C.c_void_p), ("peak_idx", C.c_void_p), ("peak_val", C.c_void_p),
         ("n_found", C.c_void_p),
         ("K_hat", C.c_void_p), ("order_crit", C.c_void_p), ("order_rule", C.c_int),
+        ("esprit_deg", C.c_void_p),
     ]
 
 
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
         "fm_subspace_sample_x": ([P, P, P, I, I, I64, P, I, I, D, P, P, P], I),
         "fm_get_knob": ([P, I, I], I),
         "fm_order": ([P, P, P, I, I64, I, P, I, D, I, P, P, P], I),
+        "fm_esprit": ([P, P, P, I, I, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -196,6 +198,11 @@ class Context:
         self.check(self.lib.fm_order(self.h, _stream(stream), _ptr(R), M, R.stride(0), T,
                                      _ptr(eig), eig.shape[0], rcond, rule, _ptr(K_hat),
                                      _ptr(crit), _ptr(status)))
+
+    def fm_esprit(self, Us, doa, status, stream=None):
+        K, M = Us.shape
+        self.check(self.lib.fm_esprit(self.h, _stream(stream), _ptr(Us), M, K, _ptr(doa),
+                                      _ptr(status)))
 
     def fm_pseudospectrum(self, Us, theta0_deg, dtheta_deg, L, P, prec=FM_FP32, stream=None):
         K, M = Us.shape

@@ -86,7 +86,7 @@ struct fm_plan {
 namespace {
 
 enum Kind { kCov, kOmega, kGather, kSketch, kSketch16, kXhv, kXz, kZx, kXcore, kGram, kSmall, kApply,
-             kSpecPrep, kRefine, kPeaks, kOrder, kAcorr, kPoly };
+             kSpecPrep, kRefine, kPeaks, kOrder, kAcorr, kPoly, kEsprit };
 
 fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
   if (ctx) {
@@ -525,9 +525,29 @@ FM_API fm_status fm_order(fm_ctx *ctx, void *stream, const void *R, int M, int64
   f.K_hat = K_hat;
   f.order_crit = crit;
   f.order_rule = rule;
-  f.order_or_status = 0;
+  f.or_status = 0;
   f.status = status;
   FM_CHECK_LAUNCH(ctx, fm::launch_order(f, nullptr, nullptr, 0, (hipStream_t)stream));
+  return FM_OK;
+}
+
+FM_API fm_status fm_esprit(fm_ctx *ctx, void *stream, const void *Us, int M, int K,
+                           double *doa_deg, uint32_t *status) {
+  if (!ctx) return FM_E_ARG;
+  if (!Us || !doa_deg || !status) return fail(ctx, FM_E_ARG, "esprit: null pointer");
+  if (M < 2 || K < 1 || K >= M)
+    return fail(ctx, FM_E_ARG, "esprit: need 1 <= K < M (K=%d M=%d)", K, M);
+  if (K > fm::kEspritMaxK) return fail(ctx, FM_E_UNSUPPORTED, "esprit: K=%d > %d", K, fm::kEspritMaxK);
+  fm_status st = set_dev(ctx);
+  if (st != FM_OK) return st;
+  FrameDev f = blank_frame();
+  f.M = M;
+  f.K = K;
+  f.Us = static_cast<double2 *>(const_cast<void *>(Us));
+  f.doa = doa_deg;
+  f.status = status;
+  f.or_status = 0;
+  FM_CHECK_LAUNCH(ctx, fm::launch_esprit(f, nullptr, nullptr, 0, (hipStream_t)stream));
   return FM_OK;
 }
 
@@ -625,6 +645,7 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kOrder: return fm::launch_order(cls, fr, it, L.count, s);
     case kAcorr: return fm::launch_acorr(cls, fr, it, L.count, s);
     case kPoly: return fm::launch_poly(cls, fr, it, L.count, L.mode, s);
+    case kEsprit: return fm::launch_esprit(cls, fr, it, L.count, s);
   }
   return hipErrorInvalidValue;
 }
@@ -664,6 +685,8 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
                      a.Us, a.sigma, a.status);
     if (st == FM_OK) st = check_spec(ctx, a.Us, a.M, a.K, a.theta0_deg, a.dtheta_deg, a.L, a.P);
     if (st == FM_OK) st = check_peaks(ctx, a.P, a.L, a.K, a.peak_idx, a.peak_val, a.n_found);
+    if (st == FM_OK && a.esprit_deg && a.K > fm::kEspritMaxK)
+      st = fail(ctx, FM_E_UNSUPPORTED, "ESPRIT: K=%d > %d", a.K, fm::kEspritMaxK);
     if (st == FM_OK && a.K_hat) {
       if (from_x)
         st = fail(ctx, FM_E_ARG, "model order: needs R (Method 1 or 2 on R, method %d)",
@@ -768,7 +791,8 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     f.K_hat = a.K_hat;
     f.order_crit = a.order_crit;
     f.order_rule = a.order_rule;
-    f.order_or_status = 1;
+    f.doa = a.esprit_deg;
+    f.or_status = 1;
     bind_ws(f, p->ws + off[i], lay[i]);
     if (grp_of[i] >= 0) {
       f.hgrp = reinterpret_cast<float2 *>(p->ws + goff[grp_of[i]]);
@@ -963,6 +987,11 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   for (int i : order)
     if (frames[i].K_hat) items.push_back({i, 0, 0, 0});
   add(p->sub, kOrder, 0, 0, b0);
+  // ESPRIT angles of the frames that ask for them
+  b0 = begin();
+  for (int i : order)
+    if (frames[i].esprit_deg) items.push_back({i, 0, 0, 0});
+  add(p->sub, kEsprit, 0, 0, b0);
 
   // spectrum (every precision): reset the recompute lists, lag sums of
   // every frame into its group buffer, then each group's polynomial pass

@@ -63,7 +63,9 @@ struct FrameDev {
   int *K_hat;           // [1]
   double *order_crit;   // [n + 1] criterion values, or null
   int order_rule;       // FM_ORDER_AIC / FM_ORDER_MDL
-  int order_or_status;  // 1: OR the order bits into *status (plans), 0: overwrite
+  // ESPRIT angles on U_s (degrees, ascending); null: none
+  double *doa;
+  int or_status;        // 1: OR the order / ESPRIT bits into *status (plans), 0: overwrite
   int nchunk;           // ceil(M / kGramRows)
   int npad;             // n rounded up to even
 };
@@ -142,6 +144,10 @@ constexpr int kZxCols = 64;  // snapshots per zx workgroup
 // workgroup per frame)
 hipError_t launch_order(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, hipStream_t s);
+// least-squares ESPRIT on U_s (one 64-lane workgroup per frame, K <= 32)
+hipError_t launch_esprit(const FrameDev &single, const FrameDev *frames, const Item *items,
+                         int n_items, hipStream_t s);
+constexpr int kEspritMaxK = 32;
 hipError_t launch_gather(const FrameDev &single, const FrameDev *frames, const Item *items,
                          int n_items, hipStream_t s);
 hipError_t launch_gram(const FrameDev &single, const FrameDev *frames, const Item *items,

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kOrderThreads) void order_kernel(FrameDev single,
   double *crit = fr.order_crit;
   int *K_hat = fr.K_hat;
   unsigned *status = fr.status;
-  const bool or_status = fr.order_or_status != 0;
+  const bool or_status = fr.or_status != 0;
 
   // trace of R: per-thread strided sums, then a fixed-shape tree (the
   // result does not depend on timing)

@@ -29,6 +29,7 @@ class FrameSpec:
     dtheta_deg: float = 0.01
     rcond: float = FM_RCOND_DEFAULT
     order_rule: int | None = None  # FM_ORDER_AIC / FM_ORDER_MDL: also estimate K (Sec. V-D)
+    esprit: bool = False           # also the ESPRIT angles of U_s (K <= 32)
 
 
 class DeviceFrame:
@@ -60,6 +61,8 @@ class DeviceFrame:
             self.order_crit = torch.zeros((s.n + 1,), dtype=torch.float64, device=dev)
         else:
             self.K_hat = self.order_crit = None
+        self.doa = (torch.zeros((s.K,), dtype=torch.float64, device=dev) if s.esprit
+                    else None)
 
     def descriptor(self) -> fm_frame:
         s = self.spec
@@ -86,6 +89,8 @@ class DeviceFrame:
             f.K_hat = self.K_hat.data_ptr()
             f.order_crit = self.order_crit.data_ptr()
             f.order_rule = s.order_rule
+        if self.doa is not None:
+            f.esprit_deg = self.doa.data_ptr()
         return f
 
     def results(self) -> dict:
@@ -98,6 +103,8 @@ class DeviceFrame:
         if self.K_hat is not None:
             out["K_hat"] = int(self.K_hat.cpu()[0])
             out["order_crit"] = self.order_crit.cpu().numpy()
+        if self.doa is not None:
+            out["doa"] = self.doa.cpu().numpy()
         return out
 
 
