@@ -31,6 +31,9 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr double kRcondOrth = 64.0 * 2.220446049250313e-16;  // orth(): drop exact zeros
+// orth() by Cholesky of the Gram unless a pivot falls below this fraction of
+// the largest diagonal entry (then the eigen route, which drops null directions)
+constexpr double kCholPivot = 1e-10;
 constexpr int kMaxSweeps = 40;
 
 template <bool kBatched>
@@ -727,6 +730,7 @@ struct SmallLds {
   int perm[kMaxN];
   int rank;
   unsigned st;
+  int chol_ok;
 };
 
 // Load a Hermitian matrix: sum of Gram partials (fixed chunk order) or a slot,
@@ -769,11 +773,75 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
   if (threadIdx.x == 0) S.st = 0u;
 
   if (mode == kOrth) {
-    // V_new = Y E diag(lambda^-1/2): orthonormal basis of the sketch
     load_herm(A, V, np, n, f.part, f.nchunk, 0, nullptr);
+    double2 *T = slot(f, kSlotT);
+    // V_new = Y L^-H with Gram = L L^H (Cholesky, lower L in A's lower
+    // triangle).  Only span(V) matters downstream (the Nystrom approximation
+    // is the same for any basis of it); a small pivot -- an ill-conditioned
+    // or rank-deficient sketch -- falls back to the eigen route below.
+    {
+      double dmax = 0.0;
+      for (int i = 0; i < n; ++i) dmax = fmax(dmax, A[(size_t)i * np + i].x);
+      if (threadIdx.x == 0) S.chol_ok = dmax > 0.0;
+      __syncthreads();
+      for (int j = 0; j < n && S.chol_ok; ++j) {
+        if (threadIdx.x == 0) {
+          double d = A[(size_t)j * np + j].x;
+          for (int k = 0; k < j; ++k) {
+            const double2 l = A[(size_t)j * np + k];
+            d -= l.x * l.x + l.y * l.y;
+          }
+          if (!(d > kCholPivot * dmax)) S.chol_ok = 0;
+          else A[(size_t)j * np + j] = make_double2(sqrt(d), 0.0);
+        }
+        __syncthreads();
+        if (!S.chol_ok) break;
+        const double ljj = A[(size_t)j * np + j].x;
+        for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
+          double2 a = A[(size_t)i * np + j];
+          for (int k = 0; k < j; ++k) {
+            // a -= L[i][k] conj(L[j][k])
+            const double2 li = A[(size_t)i * np + k], lj = A[(size_t)j * np + k];
+            a = make_double2(a.x - (li.x * lj.x + li.y * lj.y), a.y - (li.y * lj.x - li.x * lj.y));
+          }
+          A[(size_t)i * np + j] = make_double2(a.x / ljj, a.y / ljj);
+        }
+        __syncthreads();
+      }
+      if (S.chol_ok) {
+        // T = L^-H: column c of L^-1 by forward substitution (one thread per
+        // column), written conjugate-transposed
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+          for (int i = 0; i < n; ++i) {
+            double2 x = make_double2(i == c ? 1.0 : 0.0, 0.0);
+            if (i >= c) {
+              for (int k = c; k < i; ++k) {
+                const double2 l = A[(size_t)i * np + k];
+                const double2 y = V[(size_t)k * np + c];  // L^-1 column c, rows < i
+                x = make_double2(x.x - (l.x * y.x - l.y * y.y), x.y - (l.x * y.y + l.y * y.x));
+              }
+              const double lii = A[(size_t)i * np + i].x;
+              x = make_double2(x.x / lii, x.y / lii);
+            } else {
+              x = make_double2(0.0, 0.0);
+            }
+            V[(size_t)i * np + c] = x;
+          }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+          const int i = e / n, k = e % n;  // T[i][k] = conj(Linv[k][i])
+          const double2 x = V[(size_t)k * np + i];
+          T[e] = make_double2(x.x, -x.y);
+        }
+        return;
+      }
+      // the failed attempt overwrote A: reload the Gram for the eigen route
+      load_herm(A, V, np, n, f.part, f.nchunk, 0, nullptr);
+    }
+    // V_new = Y E diag(lambda^-1/2): orthonormal basis of the sketch
     const int sw = jacobi_eigh(A, V, np, S.rot, S.red);
     sort_desc(A, np, n, S.perm, S.w);
-    double2 *T = slot(f, kSlotT);
     const double thr = kRcondOrth * S.w[0];
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
       const int i = e / n, k = e % n;
