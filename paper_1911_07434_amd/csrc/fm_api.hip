@@ -563,7 +563,9 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
   const size_t uf_bytes = align256((size_t)M * K * 8);
   const size_t rl_bytes = align256((size_t)(L + 1) * 4);
   const size_t need = uf_bytes + rl_bytes +
-                      (prec == FM_FP32 ? align256((size_t)M * fm::kPolyRows * 8) : 0);
+                      (prec == FM_FP32
+                           ? align256((size_t)fm::acorr_blocks(M) * M * fm::kPolyRows * 8)
+                           : 0);
   if (need > ctx->arena_bytes)
     return fail(ctx, FM_E_WORKSPACE, "pseudospectrum: needs %zu arena bytes", need);
   if ((st = set_dev(ctx)) != FM_OK) return st;
@@ -745,7 +747,8 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     }
     for (const auto &g : groups) {
       goff.push_back(total);
-      total += align256((size_t)frames[g[0]].M * fm::kPolyRows * 8);
+      const int Mg = frames[g[0]].M;
+      total += align256((size_t)fm::acorr_blocks(Mg) * Mg * fm::kPolyRows * 8);
     }
   }
   p->ws_bytes = total;
@@ -1001,7 +1004,8 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   add(p->spec, kSpecPrep, 0, 0, b0);
   b0 = begin();
   for (int i : order)
-    for (int c = 0; c < rows(frames[i].M, fm::kAcorrLags); ++c) items.push_back({i, c, 0, 0});
+    for (int c = 0; c < rows(frames[i].M, fm::kAcorrLags); ++c)
+      for (int b = 0; b < fm::acorr_blocks(frames[i].M); ++b) items.push_back({i, c, b, 0});
   add(p->spec, kAcorr, 0, 0, b0);
   for (int per : {256, 128, 64}) {
     b0 = begin();

@@ -54,8 +54,9 @@ struct FrameDev {
   int *rlist;           // [1 + L]: count, then angles whose FP32 denominator needs FP64
   double *eig;          // [n]: every eigenvalue of S~ (descending, 0 past its rank)
   // FP32 spectrum as a polynomial in sin(theta): frames of equal M and grid
-  // share a group buffer hgrp [M][kPolyRows] (column hslot: this frame's
-  // conj(h'_d)); hmem lists the group's frames (plan indices), hcount of them
+  // share a group buffer hgrp [acorr_blocks(M)][M][kPolyRows] (column hslot:
+  // this frame's partial sums of conj(h'_d) over each block of kAcorrRows
+  // rows); hmem lists the group's frames (plan indices), hcount of them
   float2 *hgrp;
   const int *hmem;
   int hslot, hcount;
@@ -84,6 +85,8 @@ constexpr int kApplyRows = 64;     // rows per apply / gather workgroup
 constexpr int kSpecChunk = 64;     // lags staged in LDS per step of the polynomial pass
 constexpr int kPolyRows = 16;      // frames per polynomial-spectrum group (MFMA rows)
 constexpr int kAcorrLags = 256;    // lags d per autocorrelation workgroup
+constexpr int kAcorrRows = 256;    // rows m per autocorrelation workgroup (partial sums)
+__host__ __device__ inline int acorr_blocks(int M) { return (M + kAcorrRows - 1) / kAcorrRows; }
 constexpr int kRefineGroups = 4;   // FP64 recompute workgroups per frame
 constexpr int kMaxL = 64;          // max sketch width of Method 2 (l)
 constexpr int kMaxN = 256;         // max sketch width of Method 1 (p)
@@ -171,10 +174,11 @@ hipError_t launch_split(const FrameDev &single, const FrameDev *frames, const It
 hipError_t launch_spectrum16(const FrameDev &single, const FrameDev *frames, const Item *items,
                              int n_items, int nb, int nnb, hipStream_t s);
 // FP32 spectrum as a polynomial in u = sin(theta): launch_acorr writes each
-// frame's lag sums h'_d into its group buffer (one workgroup per 256 lags;
-// needs Uf and resets nothing), launch_poly evaluates a group of up to 16
-// frames over tiles of 64 nnb angles (nnb in {1, 2, 4}); items name the
-// group's first frame
+// frame's lag sums h'_d into its group buffer as partial sums over blocks of
+// kAcorrRows rows (one workgroup per 256 lags and row block; reads U_s),
+// launch_poly adds the partials in block order and evaluates a group of up
+// to 16 frames over tiles of 64 nnb angles (nnb in {1, 2, 4}); items name
+// the group's first frame
 hipError_t launch_acorr(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, hipStream_t s);
 hipError_t launch_poly(const FrameDev &single, const FrameDev *frames, const Item *items,

@@ -10,9 +10,10 @@
 // one length-M inner product per angle whatever K is, against the steering
 // vector itself.  This is the same quantity as eq. (5) in exact arithmetic.
 //
-// acorr: the lag sums h'_d of one frame in FP32 from the FP32 copy Uf of U_s
-//   (one thread per lag, the frame's columns staged through LDS; fixed
-//   summation order over k, then m).
+// acorr: the lag sums h'_d of one frame in FP32 from U_s rounded to FP32, as
+//   partial sums over blocks of 256 rows (one thread per lag, a workgroup per
+//   256 lags and row block, so no lane runs longer than 256 K products; the
+//   columns staged through LDS; fixed order over k, then m, then blocks).
 // poly:  frames with the same M and angle grid form groups of up to 16; the
 //   group's conj(h') vectors are the 16 rows of v_mfma_f32_16x16x4_f32 and the
 //   angles its columns, so each generated steering phasor and each staged
@@ -30,39 +31,53 @@ using namespace steer;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kAcM = 1024;  // rows of a column staged per acorr step
-
+// One workgroup: 256 consecutive lags d0.. (one per thread) of one frame
+// over one block of kAcorrRows rows m; the partial sums go to block `rb` of
+// the group buffer.  A lag's rows run to M - 1 - d, so blocks past that
+// contribute (and store) zeros.  Summation order within a block: k outer,
+// m ascending; the blocks are added in order by the polynomial pass.
 template <bool kBatched>
 __global__ __launch_bounds__(256) void acorr_kernel(FrameDev single, const FrameDev *frames,
                                                     const Item *items) {
-  __shared__ float2 wa[kAcM];
-  __shared__ float2 wb[kAcM + kAcorrLags];
-  int chunk;
+  __shared__ float2 wa[kAcorrRows];
+  __shared__ float2 wb[kAcorrRows + kAcorrLags];
+  int chunk, rb;
   const FrameDev *fp;
   if constexpr (kBatched) {
     const Item it = items[blockIdx.x];
     chunk = it.a;
+    rb = it.b;
     fp = frames + it.frame;
   } else {
     chunk = blockIdx.x;
+    rb = blockIdx.y;
     fp = &single;
   }
   const int M = fp->M, K = fp->K;
-  const float2 *Uf = fp->Uf;
-  float2 *hg = fp->hgrp;
+  const double2 *Us = fp->Us;
+  float2 *hg = fp->hgrp + (size_t)rb * M * kPolyRows;
   const int slot = fp->hslot;
   const int tid = threadIdx.x;
   const int d0 = chunk * kAcorrLags, d = d0 + tid;
+  const int m0 = rb * kAcorrRows;
   float re = 0.f, im = 0.f;
-  for (int k = 0; k < K; ++k) {
-    for (int m0 = 0; m0 < M - d0; m0 += kAcM) {
-      __syncthreads();  // the previous window has been read
-      for (int i = tid; i < kAcM; i += 256)
-        wa[i] = (m0 + i < M) ? Uf[(size_t)(m0 + i) * K + k] : make_float2(0.f, 0.f);
-      for (int i = tid; i < kAcM + kAcorrLags; i += 256)
-        wb[i] = (m0 + d0 + i < M) ? Uf[(size_t)(m0 + d0 + i) * K + k] : make_float2(0.f, 0.f);
+  if (m0 + d0 < M) {  // uniform: some lag of this workgroup reaches the block
+    for (int k = 0; k < K; ++k) {
+      const double2 *u = Us + (size_t)k * M;
+      __syncthreads();  // the previous column has been read
+      // FP32 roundings of U_s (the values of its FP32 copy), read along the
+      // contiguous column k; rows past M are zero
+      {
+        const int i = tid;
+        const double2 v = m0 + i < M ? u[m0 + i] : make_double2(0.0, 0.0);
+        wa[i] = make_float2((float)v.x, (float)v.y);
+      }
+      for (int i = tid; i < kAcorrRows + kAcorrLags; i += 256) {
+        const double2 v = m0 + d0 + i < M ? u[m0 + d0 + i] : make_double2(0.0, 0.0);
+        wb[i] = make_float2((float)v.x, (float)v.y);
+      }
       __syncthreads();
-      const int cnt = min(kAcM, M - d - m0);  // lags past M - 1 - m contribute nothing
+      const int cnt = min(kAcorrRows, M - d - m0);  // rows m < M - d of this block
       for (int i = 0; i < cnt; ++i) {
         // conj(U[k][m + d]) * U[k][m], m = m0 + i
         const float2 x = wb[i + tid], y = wa[i];
@@ -73,10 +88,10 @@ __global__ __launch_bounds__(256) void acorr_kernel(FrameDev single, const Frame
   }
   if (d < M) {
     if (d == 0) {
-      re *= 0.5f;  // h'_0 = h_0 / 2 (h_0 is real)
+      re *= 0.5f;  // h'_0 = h_0 / 2 (h_0 is real; halving each partial is exact)
       im = 0.f;
     }
-    hg[(size_t)d * kPolyRows + slot] = make_float2(re, -im);  // conj(h'_d)
+    hg[(size_t)d * kPolyRows + slot] = make_float2(re, -im);  // conj of the partial
   }
 }
 
@@ -105,13 +120,21 @@ __device__ __forceinline__ void poly_tile(const FrameDev &single, const FrameDev
   constexpr int kChunkElems = kSpecChunk * kPolyRows;  // 1024 float2, 4 per thread
   const int nchunk = (M + kSpecChunk - 1) / kSpecChunk;
   const size_t total = (size_t)M * kPolyRows;
+  const int nrb = acorr_blocks(M);
   float2 stage[kChunkElems / 256];
+  // conj(h'_d) of each slot: the row-block partials added in block order
   auto load_chunk = [&](int c) {
     const size_t base = (size_t)c * kChunkElems;
 #pragma unroll
     for (int j = 0; j < kChunkElems / 256; ++j) {
       const size_t e = base + tid + 256 * j;
-      stage[j] = e < total ? hg[e] : make_float2(0.f, 0.f);
+      float2 v = make_float2(0.f, 0.f);
+      if (e < total)
+        for (int b = 0; b < nrb; ++b) {
+          const float2 x = hg[(size_t)b * total + e];
+          v = make_float2(v.x + x.x, v.y + x.y);
+        }
+      stage[j] = v;
     }
   };
   auto store_chunk = [&](int buf) {
@@ -215,7 +238,8 @@ hipError_t launch_acorr(const FrameDev &single, const FrameDev *frames, const It
     hipLaunchKernelGGL(acorr_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames, items);
   } else {
     const int chunks = (single.M + kAcorrLags - 1) / kAcorrLags;
-    hipLaunchKernelGGL(acorr_kernel<false>, dim3(chunks), dim3(256), 0, s, single, frames, items);
+    hipLaunchKernelGGL(acorr_kernel<false>, dim3(chunks, acorr_blocks(single.M)), dim3(256), 0, s,
+                       single, frames, items);
   }
   return hipGetLastError();
 }
