@@ -403,7 +403,8 @@ fm_status fm_plan_run(fm_plan *plan, void *stream, int use_graph);
  *                          (one L2 holds its snapshots); 1: the frame's tiles
  *                          are dealt one by one to the least-loaded XCD.
  *   FM_KNOB_SPEC_ANGLES    bucket = ceil(K/8) - 1 (0..7).  Angles per
- *                          workgroup of the FP32 spectrum pass: 64, 128, or
+ *                          workgroup of the FP32 (polynomial) spectrum pass
+ *                          of a group of frames of that bucket: 64, 128, or
  *                          256 (buckets 0..3 only).
  *   FM_KNOB_SPEC16_ANGLES  the same for the compensated FP16 spectrum pass. */
 typedef enum {

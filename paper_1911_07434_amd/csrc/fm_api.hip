@@ -41,8 +41,10 @@ bool knob_value_ok(int knob, int bucket, int v) {
 }
 
 // built-in choices (measured on an MI355X at the 1024-channel shapes): a
-// wider angle tile reuses each staged U_s operand for more angles until
-// register pressure from the 2K stacked outputs takes over
+// wider angle tile reuses each generated phasor and staged operand for more
+// angles (in the FP16 pass until register pressure from the 2K stacked
+// outputs takes over); the best polynomial-pass tile depends on how full the
+// groups are, which the autotuner measures per batch
 int knob_default(int knob, int bucket) {
   if (knob == FM_KNOB_COV_SCHEDULE) return 0;
   return bucket < 2 ? 256 : (bucket < 6 ? 128 : 64);

@@ -11,9 +11,10 @@
 // vector itself.  This is the same quantity as eq. (5) in exact arithmetic.
 //
 // acorr: the lag sums h'_d of one frame in FP32 from U_s rounded to FP32, as
-//   partial sums over blocks of 256 rows (one thread per lag, a workgroup per
-//   256 lags and row block, so no lane runs longer than 256 K products; the
-//   columns staged through LDS; fixed order over k, then m, then blocks).
+//   partial sums over blocks of 256 rows (four adjacent lags per lane with a
+//   sliding register window, a one-wave workgroup per 256 lags and row
+//   block, so no lane runs longer than 4 x 256 K products; the columns staged
+//   through LDS; fixed order over k, then m, then blocks).
 // poly:  frames with the same M and angle grid form groups of up to 16; the
 //   group's conj(h') vectors are the 16 rows of v_mfma_f32_16x16x4_f32 and the
 //   angles its columns, so each generated steering phasor and each staged
@@ -31,16 +32,23 @@ using namespace steer;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// One workgroup: 256 consecutive lags d0.. (one per thread) of one frame
-// over one block of kAcorrRows rows m; the partial sums go to block `rb` of
-// the group buffer.  A lag's rows run to M - 1 - d, so blocks past that
-// contribute (and store) zeros.  Summation order within a block: k outer,
-// m ascending; the blocks are added in order by the polynomial pass.
+constexpr int kAcL = 4;                        // adjacent lags per lane
+constexpr int kAcThreads = kAcorrLags / kAcL;  // one wave
+
+// One workgroup (one wave): kAcorrLags consecutive lags d0.. of one frame,
+// kAcL adjacent lags per lane, over one block of kAcorrRows rows m; the
+// partial sums go to block `rb` of the group buffer.  A lane keeps the
+// kAcL values U[k][m + d] of its lags in registers and slides them by one
+// row per step (one new LDS value per kAcL products).  A lag's rows run to
+// M - 1 - d: the staged window is zero past M, so the extra products of a
+// lane's later lags add exact zeros.  Summation order within a block: k
+// outer, m ascending; the blocks are added in order by the polynomial pass.
 template <bool kBatched>
-__global__ __launch_bounds__(256) void acorr_kernel(FrameDev single, const FrameDev *frames,
-                                                    const Item *items) {
+__global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
+                                                           const FrameDev *frames,
+                                                           const Item *items) {
   __shared__ float2 wa[kAcorrRows];
-  __shared__ float2 wb[kAcorrRows + kAcorrLags];
+  __shared__ float2 wb[kAcorrRows + kAcorrLags + kAcL];
   int chunk, rb;
   const FrameDev *fp;
   if constexpr (kBatched) {
@@ -58,40 +66,61 @@ __global__ __launch_bounds__(256) void acorr_kernel(FrameDev single, const Frame
   float2 *hg = fp->hgrp + (size_t)rb * M * kPolyRows;
   const int slot = fp->hslot;
   const int tid = threadIdx.x;
-  const int d0 = chunk * kAcorrLags, d = d0 + tid;
+  const int d0 = chunk * kAcorrLags;
+  const int dl = d0 + kAcL * tid;  // this lane's first lag
   const int m0 = rb * kAcorrRows;
-  float re = 0.f, im = 0.f;
+  float re[kAcL], im[kAcL];
+#pragma unroll
+  for (int j = 0; j < kAcL; ++j) re[j] = im[j] = 0.f;
   if (m0 + d0 < M) {  // uniform: some lag of this workgroup reaches the block
     for (int k = 0; k < K; ++k) {
       const double2 *u = Us + (size_t)k * M;
       __syncthreads();  // the previous column has been read
       // FP32 roundings of U_s (the values of its FP32 copy), read along the
       // contiguous column k; rows past M are zero
-      {
-        const int i = tid;
+      for (int i = tid; i < kAcorrRows; i += kAcThreads) {
         const double2 v = m0 + i < M ? u[m0 + i] : make_double2(0.0, 0.0);
         wa[i] = make_float2((float)v.x, (float)v.y);
       }
-      for (int i = tid; i < kAcorrRows + kAcorrLags; i += 256) {
+      for (int i = tid; i < kAcorrRows + kAcorrLags + kAcL; i += kAcThreads) {
         const double2 v = m0 + d0 + i < M ? u[m0 + d0 + i] : make_double2(0.0, 0.0);
         wb[i] = make_float2((float)v.x, (float)v.y);
       }
       __syncthreads();
-      const int cnt = min(kAcorrRows, M - d - m0);  // rows m < M - d of this block
-      for (int i = 0; i < cnt; ++i) {
-        // conj(U[k][m + d]) * U[k][m], m = m0 + i
-        const float2 x = wb[i + tid], y = wa[i];
-        re = fmaf(x.x, y.x, fmaf(x.y, y.y, re));
-        im = fmaf(x.x, y.y, fmaf(-x.y, y.x, im));
+      // rows of this block used by the lane's first (longest) lag
+      const int cnt = min(kAcorrRows, M - dl - m0);
+      if (cnt > 0) {
+        const int base = kAcL * tid;
+        float2 x[kAcL];
+#pragma unroll
+        for (int j = 0; j < kAcL; ++j) x[j] = wb[base + j];
+#pragma unroll 4
+        for (int i = 0; i < cnt; ++i) {
+          const float2 y = wa[i];
+#pragma unroll
+          for (int j = 0; j < kAcL; ++j) {
+            // conj(U[k][m + d]) * U[k][m], m = m0 + i, d = dl + j
+            re[j] = fmaf(x[j].x, y.x, fmaf(x[j].y, y.y, re[j]));
+            im[j] = fmaf(x[j].x, y.y, fmaf(-x[j].y, y.x, im[j]));
+          }
+#pragma unroll
+          for (int j = 0; j + 1 < kAcL; ++j) x[j] = x[j + 1];
+          x[kAcL - 1] = wb[base + i + kAcL];
+        }
       }
     }
   }
-  if (d < M) {
-    if (d == 0) {
-      re *= 0.5f;  // h'_0 = h_0 / 2 (h_0 is real; halving each partial is exact)
-      im = 0.f;
+#pragma unroll
+  for (int j = 0; j < kAcL; ++j) {
+    const int d = dl + j;
+    if (d < M) {
+      float r = re[j], q = im[j];
+      if (d == 0) {
+        r *= 0.5f;  // h'_0 = h_0 / 2 (h_0 is real; halving each partial is exact)
+        q = 0.f;
+      }
+      hg[(size_t)d * kPolyRows + slot] = make_float2(r, -q);  // conj of the partial
     }
-    hg[(size_t)d * kPolyRows + slot] = make_float2(re, -im);  // conj of the partial
   }
 }
 
@@ -235,11 +264,12 @@ hipError_t launch_acorr(const FrameDev &single, const FrameDev *frames, const It
                         int n_items, hipStream_t s) {
   if (items) {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(acorr_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames, items);
+    hipLaunchKernelGGL(acorr_kernel<true>, dim3(n_items), dim3(kAcThreads), 0, s, single, frames,
+                       items);
   } else {
     const int chunks = (single.M + kAcorrLags - 1) / kAcorrLags;
-    hipLaunchKernelGGL(acorr_kernel<false>, dim3(chunks, acorr_blocks(single.M)), dim3(256), 0, s,
-                       single, frames, items);
+    hipLaunchKernelGGL(acorr_kernel<false>, dim3(chunks, acorr_blocks(single.M)), dim3(kAcThreads),
+                       0, s, single, frames, items);
   }
   return hipGetLastError();
 }
