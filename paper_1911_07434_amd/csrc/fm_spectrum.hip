@@ -9,8 +9,8 @@
 // polynomial in sin(theta)) or with compensated FP16 products
 // (fm_spectrum16.hip).  Both append every angle whose denominator is below
 // M/16 (the cancellation-prone main lobes) to a per-frame list, and the
-// refine kernel here recomputes those angles in FP64 from the FP64 U_s (one
-// wave per angle); a denominator below M*2^-53 is clamped there (noiseless
+// refine kernel here recomputes those angles in FP64 from the FP64 U_s (four
+// angles per wave); a denominator below M*2^-53 is clamped there (noiseless
 // on-grid pole).  Also here: the list reset of a plan and the transposed
 // FP32 copy of U_s of a single-frame call.
 #include "fm_internal.h"
@@ -35,78 +35,104 @@ __device__ __forceinline__ const FrameDev &spec_frame(const FrameDev &single,
   }
 }
 
-// FP64 denominators of the four angles Fw (one per wave; a wave with no
-// angle passes active = false but still stages and synchronises).  Each lane
-// walks every 64th channel with an FP64 phasor recurrence (64 steps at most
-// per exact start, error ~1e-14), K accumulated 16 at a time.  U_s is staged
-// through LDS 16 sources x 64 channels at a time and shared by the four
-// waves, so the workgroup reads it once per four angles.
-__device__ double den_fp64_x4(const FrameDev &f, unsigned long long F, bool active, int lane,
-                              double2 (*us)[64]) {
+constexpr int kRefAngles = 4;  // angles per wave
+constexpr int kRefK = 4;       // sources per pass over the channels
+
+// FP64 denominators of kRefAngles angles (phase frequencies F) by one wave.
+// Each lane walks every 64th channel with an FP64 phasor recurrence,
+// restarted exactly every 4096 channels (at most 64 steps per exact start,
+// error ~1e-14), and reads U_s straight from memory: the frame's waves share
+// it through the caches, and no wave waits for another.  The sources are
+// taken kRefK at a time, the angles all at once, so every U_s element loaded
+// serves kRefAngles angles.
+__device__ void den_fp64_wave(const FrameDev &f, const unsigned long long (&F)[kRefAngles],
+                              int lane, double (&den)[kRefAngles]) {
   const int M = f.M, K = f.K;
-  double proj = 0.0;
-  const double2 w = phasor64(64, F);
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const int kn = min(16, K - k0);
-    double2 acc[16];
+  double proj[kRefAngles];
+  double2 w[kRefAngles];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = make_double2(0.0, 0.0);
-    double2 a = phasor64((unsigned long long)lane, F);
-    for (int mc = 0; mc < M; mc += 64) {
-      __syncthreads();  // the previous chunk has been read by every wave
-      for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) {
-        const int k = e >> 6, m = mc + (e & 63);
-        us[k][e & 63] = (k < kn && m < M) ? f.Us[(size_t)(k0 + k) * M + m]
-                                          : make_double2(0.0, 0.0);
-      }
-      __syncthreads();
-      if (active && mc + lane < M) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          if (k < kn) {
-            const double2 u = us[k][lane];
-            // conj(u) * a
-            acc[k].x = fma(u.x, a.x, fma(u.y, a.y, acc[k].x));
-            acc[k].y = fma(u.x, a.y, fma(-u.y, a.x, acc[k].y));
-          }
-        }
-      }
-      a = make_double2(fma(a.x, w.x, -(a.y * w.y)), fma(a.x, w.y, a.y * w.x));
-    }
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      double re = acc[k].x, im = acc[k].y;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        re += __shfl_xor(re, o);
-        im += __shfl_xor(im, o);
-      }
-      if (k < kn) proj += re * re + im * im;
-    }
+  for (int j = 0; j < kRefAngles; ++j) {
+    proj[j] = 0.0;
+    w[j] = phasor64(64, F[j]);
   }
-  return (double)M - proj;
+  for (int k0 = 0; k0 < K; k0 += kRefK) {
+    const int kn = min(kRefK, K - k0);
+    const double2 *u0 = f.Us + (size_t)k0 * M;
+    double2 acc[kRefAngles][kRefK];
+    double2 a[kRefAngles];
+#pragma unroll
+    for (int j = 0; j < kRefAngles; ++j)
+#pragma unroll
+      for (int k = 0; k < kRefK; ++k) acc[j][k] = make_double2(0.0, 0.0);
+    for (int mc = 0; mc < M; mc += 64) {
+      const int m = mc + lane;
+      if ((mc & 4095) == 0) {
+#pragma unroll
+        for (int j = 0; j < kRefAngles; ++j) a[j] = phasor64((unsigned long long)m, F[j]);
+      }
+      if (m < M) {
+        double2 u[kRefK];
+#pragma unroll
+        for (int k = 0; k < kRefK; ++k)
+          u[k] = k < kn ? u0[(size_t)k * M + m] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < kRefAngles; ++j)
+#pragma unroll
+          for (int k = 0; k < kRefK; ++k) {
+            // conj(u) * a
+            acc[j][k].x = fma(u[k].x, a[j].x, fma(u[k].y, a[j].y, acc[j][k].x));
+            acc[j][k].y = fma(u[k].x, a[j].y, fma(-u[k].y, a[j].x, acc[j][k].y));
+          }
+      }
+#pragma unroll
+      for (int j = 0; j < kRefAngles; ++j)
+        a[j] = make_double2(fma(a[j].x, w[j].x, -(a[j].y * w[j].y)),
+                            fma(a[j].x, w[j].y, a[j].y * w[j].x));
+    }
+#pragma unroll
+    for (int j = 0; j < kRefAngles; ++j)
+#pragma unroll
+      for (int k = 0; k < kRefK; ++k) {
+        double re = acc[j][k].x, im = acc[j][k].y;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          re += __shfl_xor(re, o);
+          im += __shfl_xor(im, o);
+        }
+        if (k < kn) proj[j] += re * re + im * im;
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < kRefAngles; ++j) den[j] = (double)M - proj[j];
 }
 
-// FP64 recompute of the listed angles: one wave per angle, the frame's
-// kRefineGroups workgroups striding over its list
+// FP64 recompute of the listed angles: kRefAngles consecutive list entries
+// per wave, the frame's kRefineGroups workgroups of four waves striding over
+// its list
 template <bool kBatched>
 __global__ __launch_bounds__(256) void refine_kernel(FrameDev single, const FrameDev *frames,
                                                      const Item *items) {
-  __shared__ double2 us[16][64];
   int part;
   const FrameDev &f = spec_frame<kBatched>(single, frames, items, part);
   const int lane = threadIdx.x & 63;
-  const int gw = part * 4 + (threadIdx.x >> 6);
   const int cnt = f.rlist[0];
   const double floor64 = (double)f.M * 1.1102230246251565e-16;  // M * 2^-53
-  // the four waves take four consecutive list entries per step (uniform loop)
-  for (int e0 = part * 4; e0 < cnt; e0 += kRefineGroups * 4) {
-    const int e = e0 + (gw - part * 4);
-    const bool active = e < cnt;
-    const int gl = active ? f.rlist[1 + e] : 0;
-    const unsigned long long F = turn_freq(f.theta0, f.dtheta, gl);
-    const double d = den_fp64_x4(f, F, active, lane, us);
-    if (active && lane == 0) f.P[gl] = (float)(1.0 / fmax(d, floor64));
+  const int stride = kRefineGroups * 4 * kRefAngles;
+  for (int e0 = (part * 4 + (threadIdx.x >> 6)) * kRefAngles; e0 < cnt; e0 += stride) {
+    unsigned long long F[kRefAngles];
+    int gl[kRefAngles];
+#pragma unroll
+    for (int j = 0; j < kRefAngles; ++j) {
+      gl[j] = e0 + j < cnt ? f.rlist[1 + e0 + j] : -1;
+      F[j] = gl[j] >= 0 ? turn_freq(f.theta0, f.dtheta, gl[j]) : 0ull;
+    }
+    double d[kRefAngles];
+    den_fp64_wave(f, F, lane, d);
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < kRefAngles; ++j)
+        if (gl[j] >= 0) f.P[gl[j]] = (float)(1.0 / fmax(d[j], floor64));
+    }
   }
 }
 
