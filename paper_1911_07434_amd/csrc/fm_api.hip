@@ -88,7 +88,7 @@ struct fm_plan {
 namespace {
 
 enum Kind { kCov, kOmega, kGather, kSketch, kSketch16, kXhv, kXz, kZx, kXcore, kGram, kSmall, kApply,
-             kSpecPrep, kRefine, kPeaks, kOrder, kAcorr, kPoly, kEsprit };
+             kSpecPrep, kRefine, kPeaks, kOrder, kAcorr, kHsum, kPoly, kEsprit };
 
 fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
   if (ctx) {
@@ -591,6 +591,7 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
     f.hcount = 1;
     FM_CHECK_LAUNCH(ctx, fm::launch_uf(f, s));
     FM_CHECK_LAUNCH(ctx, fm::launch_acorr(f, nullptr, nullptr, 0, s));
+    if (fm::acorr_blocks(M) > 1) FM_CHECK_LAUNCH(ctx, fm::launch_hsum(f, nullptr, nullptr, 0, s));
     FM_CHECK_LAUNCH(ctx, fm::launch_poly(f, nullptr, nullptr, 0, nnb, s));
   } else {
     const int nnb = ctx->knob[FM_KNOB_SPEC16_ANGLES][nb - 1] / 64;
@@ -648,6 +649,7 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kPeaks: return fm::launch_peaks(cls, fr, it, L.count, s);
     case kOrder: return fm::launch_order(cls, fr, it, L.count, s);
     case kAcorr: return fm::launch_acorr(cls, fr, it, L.count, s);
+    case kHsum: return fm::launch_hsum(cls, fr, it, L.count, s);
     case kPoly: return fm::launch_poly(cls, fr, it, L.count, L.mode, s);
     case kEsprit: return fm::launch_esprit(cls, fr, it, L.count, s);
   }
@@ -999,8 +1001,9 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   add(p->sub, kEsprit, 0, 0, b0);
 
   // spectrum (every precision): reset the recompute lists, lag sums of
-  // every frame into its group buffer, then each group's polynomial pass
-  // (tiles of the knob's width for the group's bucket)
+  // every frame into its group buffer (row-block partials, then their sums
+  // per group), then each group's polynomial pass (tiles of the knob's width
+  // for the group's bucket)
   b0 = begin();
   for (int i : order) items.push_back({i, 0, 0, 0});
   add(p->spec, kSpecPrep, 0, 0, b0);
@@ -1009,6 +1012,11 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     for (int c = 0; c < rows(frames[i].M, fm::kAcorrLags); ++c)
       for (int b = 0; b < fm::acorr_blocks(frames[i].M); ++b) items.push_back({i, c, b, 0});
   add(p->spec, kAcorr, 0, 0, b0);
+  b0 = begin();
+  for (const auto &g : groups)
+    if (fm::acorr_blocks(frames[g[0]].M) > 1)
+      for (int c = 0; c < fm::hsum_chunks(frames[g[0]].M); ++c) items.push_back({g[0], c, 0, 0});
+  add(p->spec, kHsum, 0, 0, b0);
   for (int per : {256, 128, 64}) {
     b0 = begin();
     for (const auto &g : groups) {

@@ -176,11 +176,15 @@ hipError_t launch_spectrum16(const FrameDev &single, const FrameDev *frames, con
 // FP32 spectrum as a polynomial in u = sin(theta): launch_acorr writes each
 // frame's lag sums h'_d into its group buffer as partial sums over blocks of
 // kAcorrRows rows (one workgroup per 256 lags and row block; reads U_s),
-// launch_poly adds the partials in block order and evaluates a group of up
-// to 16 frames over tiles of 64 nnb angles (nnb in {1, 2, 4}); items name
-// the group's first frame
+// launch_hsum adds a group's partials in block order into the first block
+// (hsum_chunks(M) workgroups per group), launch_poly evaluates a group of up
+// to 16 frames over tiles of 64 nnb angles (nnb in {1, 2, 4}); the items of
+// the last two name the group's first frame
 hipError_t launch_acorr(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, hipStream_t s);
+int hsum_chunks(int M);
+hipError_t launch_hsum(const FrameDev &single, const FrameDev *frames, const Item *items,
+                       int n_items, hipStream_t s);
 hipError_t launch_poly(const FrameDev &single, const FrameDev *frames, const Item *items,
                        int n_items, int nnb, hipStream_t s);
 hipError_t launch_refine(const FrameDev &single, const FrameDev *frames, const Item *items,

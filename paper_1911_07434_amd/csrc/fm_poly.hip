@@ -14,7 +14,9 @@
 //   partial sums over blocks of 256 rows (four adjacent lags per lane with a
 //   sliding register window, a one-wave workgroup per 256 lags and row
 //   block, so no lane runs longer than 4 x 256 K products; the columns staged
-//   through LDS; fixed order over k, then m, then blocks).
+//   through LDS; fixed order over k, then m).
+// hsum:  adds each group's row-block partials in block order, once, into the
+//   first block, which the polynomial pass then reads.
 // poly:  frames with the same M and angle grid form groups of up to 16; the
 //   group's conj(h') vectors are the 16 rows of v_mfma_f32_16x16x4_f32 and the
 //   angles its columns, so each generated steering phasor and each staged
@@ -124,6 +126,33 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
   }
 }
 
+// Row-block partials of a group buffer added in block order (starting from
+// zero, as the sums of the single-block case) into the first block: one
+// workgroup per kHsumElems entries of the group's M x kPolyRows lag sums.
+constexpr int kHsumElems = 1024;
+
+template <bool kBatched>
+__global__ __launch_bounds__(256) void hsum_kernel(FrameDev single, const FrameDev *frames,
+                                                   const Item *items) {
+  const FrameDev &g = kBatched ? frames[items[blockIdx.x].frame] : single;
+  const int chunk = kBatched ? items[blockIdx.x].a : blockIdx.x;
+  const size_t total = (size_t)g.M * kPolyRows;
+  const int nrb = acorr_blocks(g.M);
+  float2 *hg = g.hgrp;
+#pragma unroll
+  for (int j = 0; j < kHsumElems / 256; ++j) {
+    const size_t e = (size_t)chunk * kHsumElems + threadIdx.x + 256 * j;
+    if (e < total) {
+      float2 v = make_float2(0.f, 0.f);
+      for (int b = 0; b < nrb; ++b) {
+        const float2 x = hg[(size_t)b * total + e];
+        v = make_float2(v.x + x.x, v.y + x.y);
+      }
+      hg[e] = v;
+    }
+  }
+}
+
 // one tile of 64 NNB angles of a group (four waves of 16 NNB angles); the
 // group buffer is staged through LDS in chunks of kSpecChunk lags, double
 // buffered like the per-frame pass
@@ -149,21 +178,14 @@ __device__ __forceinline__ void poly_tile(const FrameDev &single, const FrameDev
   constexpr int kChunkElems = kSpecChunk * kPolyRows;  // 1024 float2, 4 per thread
   const int nchunk = (M + kSpecChunk - 1) / kSpecChunk;
   const size_t total = (size_t)M * kPolyRows;
-  const int nrb = acorr_blocks(M);
   float2 stage[kChunkElems / 256];
-  // conj(h'_d) of each slot: the row-block partials added in block order
+  // conj(h'_d) of each slot (the sums hsum left in the first block)
   auto load_chunk = [&](int c) {
     const size_t base = (size_t)c * kChunkElems;
 #pragma unroll
     for (int j = 0; j < kChunkElems / 256; ++j) {
       const size_t e = base + tid + 256 * j;
-      float2 v = make_float2(0.f, 0.f);
-      if (e < total)
-        for (int b = 0; b < nrb; ++b) {
-          const float2 x = hg[(size_t)b * total + e];
-          v = make_float2(v.x + x.x, v.y + x.y);
-        }
-      stage[j] = v;
+      stage[j] = e < total ? hg[e] : make_float2(0.f, 0.f);
     }
   };
   auto store_chunk = [&](int buf) {
@@ -270,6 +292,20 @@ hipError_t launch_acorr(const FrameDev &single, const FrameDev *frames, const It
     const int chunks = (single.M + kAcorrLags - 1) / kAcorrLags;
     hipLaunchKernelGGL(acorr_kernel<false>, dim3(chunks, acorr_blocks(single.M)), dim3(kAcThreads),
                        0, s, single, frames, items);
+  }
+  return hipGetLastError();
+}
+
+int hsum_chunks(int M) { return (M * kPolyRows + kHsumElems - 1) / kHsumElems; }
+
+hipError_t launch_hsum(const FrameDev &single, const FrameDev *frames, const Item *items,
+                       int n_items, hipStream_t s) {
+  if (items) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(hsum_kernel<true>, dim3(n_items), dim3(256), 0, s, single, frames, items);
+  } else {
+    hipLaunchKernelGGL(hsum_kernel<false>, dim3(hsum_chunks(single.M)), dim3(256), 0, s, single,
+                       frames, items);
   }
   return hipGetLastError();
 }
