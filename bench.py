@@ -235,7 +235,8 @@ def main():
                     help="extra legs after the main step: compare (mixed precision, Method 1, "
                          "standard MUSIC, latency alone), uneven (512-frame uneven batch), "
                          "serve (Poisson serving trace)")
-    ap.add_argument("--prec", choices=("fp32", "fp16", "bf16"), default="fp32",
+    ap.add_argument("--prec", choices=("fp32", "fp16", "bf16", "fp16x3", "bf16x3"),
+                    default="fp32",
                     help="covariance operand precision of the main timed step")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the Poisson arrival trace of the serving leg (0 = skip)")
@@ -295,7 +296,9 @@ def main():
         return out
 
     frames2 = make_frames(fm.FM_METHOD_PROJECT)
-    main_prec = {"fp32": fm.FM_FP32, "fp16": fm.FM_FP16, "bf16": fm.FM_BF16}[args.prec]
+    precs = {"fp32": fm.FM_FP32, "fp16": fm.FM_FP16, "bf16": fm.FM_BF16,
+             "fp16x3": fm.FM_FP16X3, "bf16x3": fm.FM_BF16X3}
+    main_prec = precs[args.prec]
     plan2 = fm.Plan(ctx, [d.descriptor() for d in frames2], prec=main_prec)
     log(f"plan workspace {plan2.workspace_bytes() / 2**20:.0f} MiB")
 
@@ -369,8 +372,13 @@ def main():
 
     if "compare" in legs:
         # ---- mixed precision: 16-bit covariance operands, same frames ------
+        # (the split precisions are checked against the main step's spectra of
+        # the first frames)
+        n_chk = 8
+        P_main = [frames2[i].P.double().cpu().numpy() for i in range(n_chk)]
         mixed = {}
-        for pname, prec in (("fp16", fm.FM_FP16), ("bf16", fm.FM_BF16)):
+        for pname, prec in (("fp16", fm.FM_FP16), ("bf16", fm.FM_BF16),
+                            ("fp16x3", fm.FM_FP16X3), ("bf16x3", fm.FM_BF16X3)):
             planm = fm.Plan(ctx, [d.descriptor() for d in frames2], prec=prec)
             with torch.cuda.stream(stream):
                 step(planm)
@@ -390,11 +398,21 @@ def main():
                             "stage_ms_per_step": {k: round(v, 4) for k, v in sm.items()},
                             "covariance_tflops": round(am, 1),
                             "covariance_frac_of_16bit_peak": round(am / PEAK_F16_MFMA_TFLOPS, 4)}
-            log(f"mixed {pname}: {vm:.1f} frames/s, stages {sm}")
+            if pname.endswith("x3"):
+                # three 16-bit products per complex product: matrix-core work
+                # is three times the algorithmic count
+                mixed[pname]["covariance_mfma_frac_of_16bit_peak"] = round(
+                    3 * am / PEAK_F16_MFMA_TFLOPS, 4)
+            dP = max(float(np.max(np.abs(10 * np.log10(
+                frames2[i].P.double().cpu().numpy() / P_main[i])))) for i in range(n_chk))
+            mixed[pname]["max_abs_dP_dB_vs_main_step"] = float(f"{dP:.3g}")
+            log(f"mixed {pname}: {vm:.1f} frames/s, stages {sm}, max |dP| vs main {dP:.3g} dB")
             del planm
         out["mixed_precision"] = mixed
         out["mixed_precision_note"] = ("covariance operands in FP16/BF16 with FP32 "
-                                       "accumulation; Method 2 sketch on FP16 matrix cores "
+                                       "accumulation (fp16x3/bf16x3: operands split into "
+                                       "16-bit hi+lo halves, three products, FP32-level "
+                                       "error); Method 2 sketch on FP16 matrix cores "
                                        "with hi+lo split operands (three products, FP32 "
                                        "accumulation); spectrum FP32 (polynomial pass); small "
                                        "dense steps and peak-region denominators FP64")

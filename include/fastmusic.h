@@ -64,16 +64,23 @@ typedef enum {
 /* Operand precision of the matrix-core products.  Accumulation is FP32 in
  * every mode.
  *   covariance (fm_covariance, stage 1 of a plan): operands rounded to the
- *     given precision.
+ *     given precision.  FM_FP16X3 and FM_BF16X3 write each snapshot as
+ *     hi + lo (hi its 16-bit rounding, lo the 16-bit rounding of the
+ *     remainder) and accumulate lo*hi + hi*lo + hi*hi on the 16-bit matrix
+ *     cores: FP32-level error (22 significant bits per operand with FP16,
+ *     16 with BF16) at three 16-bit products per complex product.  FP16
+ *     halves keep 22 bits for snapshots of magnitude >= 2^-3 (below that lo
+ *     loses bits: absolute error <= 2^-25 per value); BF16 has FP32's range.
  *   pseudo-spectrum (fm_pseudospectrum): FM_FP32 evaluates the spectrum as a
  *     polynomial in sin(theta) on FP32 products (one length-M product per
  *     angle, see fm_pseudospectrum); FM_FP16 splits U_s and the steering
  *     twiddles into FP16 hi + lo halves and accumulates hi*hi + hi*lo +
- *     lo*hi (~22-bit products), K products per angle.  fm_pseudospectrum
- *     rejects FM_BF16 (FM_E_UNSUPPORTED).  Plans at every precision run the
+ *     lo*hi (~22-bit products), K products per angle; FM_FP16X3 is the
+ *     same pass.  fm_pseudospectrum rejects FM_BF16 and FM_BF16X3
+ *     (FM_E_UNSUPPORTED).  Plans at every precision run the
  *     FP32 polynomial pass (faster and more accurate than the FP16 one).
  *   sketch products Y = R V (fm_subspace_project, stage 2 of a plan):
- *     FM_FP32 uses FP32 products; FM_FP16 and FM_BF16 split R and V into
+ *     FM_FP32 uses FP32 products; every 16-bit precision splits R and V into
  *     FP16 hi + lo halves (power-of-two scaled) and accumulate hi*hi + hi*lo
  *     + lo*hi, for sketch widths l <= 32 (wider sketches use FP32 products).
  *     A plain 16-bit rounding of R would move the peak-region denominators
@@ -84,7 +91,9 @@ typedef enum {
 typedef enum {
   FM_FP32 = 0,   /* FP32 operands on FP32 MFMA */
   FM_BF16 = 1,   /* BF16 operands on BF16 MFMA */
-  FM_FP16 = 2    /* FP16 operands on FP16 MFMA */
+  FM_FP16 = 2,   /* FP16 operands on FP16 MFMA */
+  FM_FP16X3 = 3, /* FP16 hi + lo operands, three products, on FP16 MFMA */
+  FM_BF16X3 = 4  /* BF16 hi + lo operands, three products, on BF16 MFMA */
 } fm_prec;
 
 /* Subspace method of a frame in a plan. */

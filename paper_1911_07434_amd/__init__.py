@@ -17,7 +17,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfastmusic.so")
 
 FM_OK, FM_E_ARG, FM_E_HIP, FM_E_WORKSPACE, FM_E_UNSUPPORTED = 0, 1, 2, 3, 4
-FM_FP32, FM_BF16, FM_FP16 = 0, 1, 2
+FM_FP32, FM_BF16, FM_FP16, FM_FP16X3, FM_BF16X3 = 0, 1, 2, 3, 4
 FM_METHOD_PROJECT, FM_METHOD_SAMPLE, FM_METHOD_PROJECT_X, FM_METHOD_SAMPLE_X = 0, 1, 2, 3
 FM_ST_NONFINITE, FM_ST_EIG_MAXIT, FM_ST_RANK_DEFICIENT, FM_ST_FEW_PEAKS, FM_ST_BAD_INDEX = (
     1, 4, 8, 16, 32)

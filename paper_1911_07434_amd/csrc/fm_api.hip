@@ -152,7 +152,9 @@ FrameDev blank_frame() {
   return f;
 }
 
-bool prec_ok(fm_prec p) { return p == FM_FP32 || p == FM_BF16 || p == FM_FP16; }
+bool prec_ok(fm_prec p) {
+  return p == FM_FP32 || p == FM_BF16 || p == FM_FP16 || p == FM_FP16X3 || p == FM_BF16X3;
+}
 
 fm_status set_dev(fm_ctx *ctx) {
   hipError_t e = hipSetDevice(ctx->device);
@@ -560,8 +562,9 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
   fm_status st = check_spec(ctx, Us, M, K, theta0_deg, dtheta_deg, L, P);
   if (st != FM_OK) return st;
   if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "pseudospectrum: bad precision %d", (int)prec);
-  if (prec == FM_BF16)
-    return fail(ctx, FM_E_UNSUPPORTED, "pseudospectrum: FM_FP32 or FM_FP16 (compensated) only");
+  if (prec == FM_BF16 || prec == FM_BF16X3)
+    return fail(ctx, FM_E_UNSUPPORTED,
+                "pseudospectrum: FM_FP32 or FM_FP16 / FM_FP16X3 (compensated) only");
   const size_t uf_bytes = align256((size_t)M * K * 8);
   const size_t rl_bytes = align256((size_t)(L + 1) * 4);
   const size_t need = uf_bytes + rl_bytes +

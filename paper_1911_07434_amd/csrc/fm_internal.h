@@ -107,7 +107,8 @@ enum ApplyMode { kApplyV = 0, kApplyUs = 1 };
 // ---------------------------------------------------------------------------
 hipError_t launch_covariance(const FrameDev &single, const FrameDev *frames,
                              const Item *items, int n_items, fm_prec prec, hipStream_t s);
-// 16-bit operand covariance (FM_FP16 / FM_BF16), FP32 accumulation
+// 16-bit operand covariance (FM_FP16 / FM_BF16, or split hi + lo with
+// FM_FP16X3 / FM_BF16X3), FP32 accumulation
 hipError_t launch_covariance16(const FrameDev &single, const FrameDev *frames,
                                const Item *items, int n_items, fm_prec prec, hipStream_t s);
 hipError_t launch_omega(const FrameDev &single, const FrameDev *frames, const Item *items,

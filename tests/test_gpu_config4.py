@@ -3,7 +3,8 @@
 M = 4096 channels, T = 8192 snapshots, K = 16 sources as eight pairs 0.5 deg
 apart, SNR in {-10, 0, 10, 30} dB, Method 2 with l = 24, q = 2, and a
 36001-angle grid at 0.005 deg.  The covariance runs with FP32, FP16 and
-BF16 operands (FP32 accumulation); the oracle runs the whole pipeline in
+BF16 operands (FP32 accumulation), and with split FP16 / BF16 hi + lo
+operands; the oracle runs the whole pipeline in
 FP64 on the same complex64 snapshots and Gaussian test matrix.  The error
 of every path is printed per SNR.
 """
@@ -24,7 +25,9 @@ M, T, K, L_SK, Q, L = 4096, 8192, 16, 24, 2, 36001
 # meet the mixed budget up to 10 dB; at 30 dB the peak-region denominators
 # are so small that BF16 rounding of the snapshots moves them by ~0.015 dB
 # (measured on an MI355X), so BF16 is reported but not asserted there.
-BARS_DB = {"fp32": 1e-3, "fp16": 1e-2, "bf16": 1e-2}
+# The split precisions (hi + lo halves, three 16-bit products) carry
+# FP32-level error and are held to the FP32 bar at every SNR.
+BARS_DB = {"fp32": 1e-3, "fp16": 1e-2, "bf16": 1e-2, "fp16x3": 1e-3, "bf16x3": 1e-3}
 
 
 @pytest.fixture(scope="module")
@@ -48,7 +51,8 @@ def test_config4_mixed_precision_per_snr(ctx, snr):
     X = torch.from_numpy(fr.X).cuda()
     Omd = torch.from_numpy(Om).cuda()
     got = {}
-    for name, prec in (("fp32", fm.FM_FP32), ("fp16", fm.FM_FP16), ("bf16", fm.FM_BF16)):
+    for name, prec in (("fp32", fm.FM_FP32), ("fp16", fm.FM_FP16), ("bf16", fm.FM_BF16),
+                       ("fp16x3", fm.FM_FP16X3), ("bf16x3", fm.FM_BF16X3)):
         d = DeviceFrame(spec, X=X, rnd=Omd)
         plan = fm.Plan(ctx, [d.descriptor()], prec=prec)
         plan.run()

@@ -526,14 +526,16 @@ def test_argument_validation(ctx):
 # ----------------------------------------------------------------------------
 
 DB_MIXED = 1e-2
-PRECS = {"fp16": fm.FM_FP16, "bf16": fm.FM_BF16}
+PRECS = {"fp16": fm.FM_FP16, "bf16": fm.FM_BF16, "fp16x3": fm.FM_FP16X3,
+         "bf16x3": fm.FM_BF16X3}
 
 
-@pytest.mark.parametrize("prec", ["fp16", "bf16"])
-@pytest.mark.parametrize("M,T", [(8, 64), (200, 512), (257, 2048)])
+@pytest.mark.parametrize("prec", ["fp16", "bf16", "fp16x3", "bf16x3"])
+@pytest.mark.parametrize("M,T", [(8, 64), (200, 512), (257, 2048), (130, 8)])
 def test_covariance16_integer_bitwise(ctx, prec, M, T):
-    # |re|, |im| <= 8 are exact in FP16 and BF16; every partial sum is an
-    # exact integer in FP32, so the result is the oracle's bit for bit
+    # |re|, |im| <= 8 are exact in FP16 and BF16 (the split precisions' lo
+    # halves are zero); every partial sum is an exact integer in FP32, so the
+    # result is the oracle's bit for bit
     say(f"cov16 int {prec} M={M} T={T}")
     X = fmsynth.make_integer_frame(M, T, seed=3 * M + T)
     R = torch.empty((M, M), dtype=torch.complex64, device="cuda")
@@ -556,6 +558,29 @@ def test_covariance16_gaussian(ctx, prec, tol, M, T):
     Rg = R.cpu().numpy()
     Ro = oracle.covariance(fr.X, threads=oracle.default_threads())
     assert np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro) <= tol
+    assert np.array_equal(Rg, Rg.conj().T)
+    assert np.all(np.diag(Rg).imag == 0)
+
+
+# split operands x = hi + lo: the representation error of each snapshot is at
+# most u_s |x| with u_s = 2^-22 (FP16 halves) or 2^-17 (BF16 halves), and the
+# dropped lo*lo term at most u_s^2-ish, so each product moves by about 2 u_s
+# relative on top of the FP32 accumulation error that the FP32 path's 1e-6
+# bar already covers
+@pytest.mark.parametrize("prec,tol", [("fp16x3", 1e-6 + 2 * 2.0 ** -22),
+                                      ("bf16x3", 1e-6 + 2 * 2.0 ** -17)])
+@pytest.mark.parametrize("M,T", [(64, 128), (300, 777), (130, 3), (1, 5), (1024, 2048)])
+def test_covariance_split_gaussian(ctx, prec, tol, M, T):
+    say(f"cov split gauss {prec} M={M} T={T}")
+    fr = fmsynth.make_frame(M, T, min(3, M), 0.0, seed=M + 11 * T)
+    R = torch.empty((M, M), dtype=torch.complex64, device="cuda")
+    ctx.fm_covariance(dev(fr.X), R, prec=PRECS[prec])
+    torch.cuda.synchronize()
+    Rg = R.cpu().numpy()
+    Ro = oracle.covariance(fr.X, threads=oracle.default_threads())
+    err = np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)
+    say(f"  relative Frobenius error {err:.3g}")
+    assert err <= tol
     assert np.array_equal(Rg, Rg.conj().T)
     assert np.all(np.diag(Rg).imag == 0)
 
@@ -594,9 +619,47 @@ def test_mixed_fp16_end_to_end(ctx, name, method, seed):
         assert np.min(np.abs(got["peak_idx"] - pk)) <= 1
 
 
+# split precisions carry FP32-level error: the FP32 path's spectrum bar
+@pytest.mark.parametrize("prec", ["fp16x3", "bf16x3"])
+@pytest.mark.parametrize("name,method,seed", [("c1", "project", 41), ("c2", "project", 42),
+                                              ("c2", "sample", 43)])
+def test_split_end_to_end(ctx, prec, name, method, seed):
+    say(f"split {prec} {name} {method}")
+    got, ref = _plan_one(ctx, name, method, seed, PRECS[prec])
+    err = db_err(got["P"], ref["P"])
+    say(f"  max |dP| = {err:.3g} dB")
+    assert got["status"] == 0
+    assert err <= DB_FP32
+    assert got["n_found"] == len(ref["peak_idx"])
+    for pk in ref["peak_idx"]:
+        assert np.min(np.abs(got["peak_idx"] - pk)) <= 1
+
+
+def test_split_precision_calls(ctx):
+    # FP16X3 takes the compensated FP16 spectrum pass; BF16X3 has none
+    M, K = 64, 2
+    Us = torch.zeros((K, M), dtype=torch.complex128, device="cuda")
+    Us[0, 0] = 1.0
+    Us[1, 1] = 1.0
+    P = torch.empty(91, dtype=torch.float32, device="cuda")
+    Pr = torch.empty(91, dtype=torch.float32, device="cuda")
+    ctx.fm_pseudospectrum(Us, -90.0, 2.0, 91, P, prec=fm.FM_FP16X3)
+    ctx.fm_pseudospectrum(Us, -90.0, 2.0, 91, Pr, prec=fm.FM_FP16)
+    torch.cuda.synchronize()
+    assert torch.equal(P, Pr)
+    with pytest.raises(fm.FmError) as e:
+        ctx.fm_pseudospectrum(Us, -90.0, 2.0, 91, P, prec=fm.FM_BF16X3)
+    assert e.value.status == fm.FM_E_UNSUPPORTED
+    R = torch.zeros((M, M), dtype=torch.complex64, device="cuda")
+    X = torch.zeros((M, 4), dtype=torch.complex64, device="cuda")
+    with pytest.raises(fm.FmError) as e:
+        ctx.fm_covariance(X, R, prec=5)                                 # no such precision
+    assert e.value.status == fm.FM_E_ARG
+
+
 def test_mixed_plan_equals_single_calls_bitwise(ctx):
     frames = _mixed_frames(5, seed=9)
-    for prec in (fm.FM_FP16, fm.FM_BF16):
+    for prec in (fm.FM_FP16, fm.FM_BF16, fm.FM_FP16X3, fm.FM_BF16X3):
         alone = []
         for spec, X, rnd in frames:
             d = DeviceFrame(spec, X=torch.from_numpy(X), rnd=torch.from_numpy(rnd))
