@@ -96,20 +96,38 @@ __global__ __launch_bounds__(256) void sketch16_kernel(FrameDev single, const Fr
     if (col >= 2 * n) bsm[e] = (_Float16)0.f;
   }
 
-  // B staging: the V chunk (kCh x n complex) as split columns
-  auto stage_b = [&](int c, int buf) {
+  // B staging in two steps, so that the chunk's MFMAs run between them and
+  // the wait for V never waits for the R prefetch issued after it: load the
+  // V chunk (kCh x n complex, row-major) into registers (elements past `lim`,
+  // rows past M, come from a valid address and are stored as zero), then
+  // split it into hi / lo columns in LDS
+  constexpr int JB = (kCh * 16 * NB + 255) / 256;
+  f32x2 vreg[JB];
+  // (global-address-space loads: a flat load's wait would also wait for the
+  // R prefetch and the LDS traffic)
+  const gf32x2 *Vg = (const gf32x2 *)V;
+  auto load_b = [&](int c, int lim) {
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      const int e = min(tid + 256 * j, lim - 1);
+      vreg[j] = Vg[(size_t)c * kCh * n + e];
+    }
+  };
+  auto store_b = [&](int buf, int lim) {
     _Float16 *bh = bsm + buf * 2 * kPlane, *bl = bh + kPlane;
-    for (int e = tid; e < kCh * n; e += blockDim.x) {
-      const int ml = e / n, cc = e % n, m = c * kCh + ml;
-      float2 v = make_float2(0.f, 0.f);
-      if (m < M) v = V[(size_t)m * n + cc];
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      const int e = tid + 256 * j;
+      if (e >= kCh * n) continue;
+      const int ml = e / n, cc = e % n;
+      const f32x2 v = e < lim ? vreg[j] : f32x2{0.f, 0.f};
       const float vr = v.x * sV, vi = v.y * sV;
       const float q[4] = {vr, -vi, vi, vr};   // Re column: (vr, -vi); Im column: (vi, vr)
       _Float16 qh[4], ql[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        qh[j] = (_Float16)q[j];
-        ql[j] = (_Float16)(q[j] - (float)qh[j]);
+      for (int k = 0; k < 4; ++k) {
+        qh[k] = (_Float16)q[k];
+        ql[k] = (_Float16)(q[k] - (float)qh[k]);
       }
       const int ore = cc * kBRow + 2 * ml, oim = (n + cc) * kBRow + 2 * ml;
       bh[ore] = qh[0];
@@ -127,34 +145,36 @@ __global__ __launch_bounds__(256) void sketch16_kernel(FrameDev single, const Fr
   // 8 ks + 4 h .. + 3 of its row = two float4
   const int row = min(i0 + r, M - 1);
   const float *Rrow = reinterpret_cast<const float *>(R + (size_t)row * ldr);
-  auto load_r = [&](f32x4 (&a)[8], int c) {
+  // a chunk inside M: unconditional loads
+  auto load_r_full = [&](f32x4 (&a)[8], int c) {
     const int mb = c * kCh;
-    if (mb + kCh <= M) {
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
+    for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-          a[2 * ks + q] = *(gf32x4 *)(Rrow + 2 * (mb + 8 * ks + 4 * h + 2 * q));
-    } else {
+      for (int q = 0; q < 2; ++q)
+        a[2 * ks + q] = *(gf32x4 *)(Rrow + 2 * (mb + 8 * ks + 4 * h + 2 * q));
+  };
+  // the ragged last chunk: channels past M read as zero
+  auto load_r_tail = [&](f32x4 (&a)[8], int c) {
+    const int mb = c * kCh;
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
+    for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int m = mb + 8 * ks + 4 * h + 2 * q;
-          f32x4 x = f32x4{0.f, 0.f, 0.f, 0.f};
-          if (m < M) {
-            const f32x2 y = *(gf32x2 *)(Rrow + 2 * m);
-            x.x = y.x;
-            x.y = y.y;
-          }
-          if (m + 1 < M) {
-            const f32x2 y = *(gf32x2 *)(Rrow + 2 * (m + 1));
-            x.z = y.x;
-            x.w = y.y;
-          }
-          a[2 * ks + q] = x;
+      for (int q = 0; q < 2; ++q) {
+        const int m = mb + 8 * ks + 4 * h + 2 * q;
+        f32x4 x = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (m < M) {
+          const f32x2 y = *(gf32x2 *)(Rrow + 2 * m);
+          x.x = y.x;
+          x.y = y.y;
         }
-    }
+        if (m + 1 < M) {
+          const f32x2 y = *(gf32x2 *)(Rrow + 2 * (m + 1));
+          x.z = y.x;
+          x.w = y.y;
+        }
+        a[2 * ks + q] = x;
+      }
   };
 
   floatx16 acc[NB];
@@ -181,28 +201,44 @@ __global__ __launch_bounds__(256) void sketch16_kernel(FrameDev single, const Fr
     }
   };
 
-  const int nchunk = (M + kCh - 1) / kCh;
+  // full chunks: the prefetch of chunk c + 1 is clamped to the last full
+  // chunk (a repeat hits the cache), so every load in the loop is
+  // unconditional and the compiler's waits cover only what each step uses
+  const int nfull = M / kCh;
+  const int vfull = kCh * n;
   f32x4 a0[8], a1[8];
   __syncthreads();  // zero columns written before any staging
-  stage_b(0, 0);
-  load_r(a0, 0);
-  __syncthreads();
-  for (int c = 0; c < nchunk; c += 2) {
-    const bool has1 = c + 1 < nchunk;
-    if (has1) {
-      load_r(a1, c + 1);
-      stage_b(c + 1, 1);
+  if (nfull > 0) {
+    load_b(0, vfull);
+    load_r_full(a0, 0);
+    store_b(0, vfull);
+    __syncthreads();
+    for (int c = 0; c < nfull; c += 2) {
+      const int c1 = min(c + 1, nfull - 1);
+      load_b(c1, vfull);
+      load_r_full(a1, c1);
+      __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
+      compute(a0, 0);
+      store_b(1, vfull);
+      __syncthreads();
+      if (c + 1 >= nfull) break;
+      const int c2 = min(c + 2, nfull - 1);
+      load_b(c2, vfull);
+      load_r_full(a0, c2);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, 1);
+      store_b(0, vfull);
+      __syncthreads();
     }
+  }
+  if (nfull * kCh < M) {
+    // ragged last chunk; buffer 0 is free (every wave passed the last barrier)
+    load_b(nfull, (M - nfull * kCh) * n);
+    load_r_tail(a0, nfull);
+    store_b(0, (M - nfull * kCh) * n);
+    __syncthreads();
     compute(a0, 0);
-    __syncthreads();
-    if (!has1) break;
-    const bool has2 = c + 2 < nchunk;
-    if (has2) {
-      load_r(a0, c + 2);
-      stage_b(c + 2, 0);
-    }
-    compute(a1, 1);
-    __syncthreads();
+    __syncthreads();  // the epilogue reuses the LDS buffers
   }
 
   // store Y (unscaled), Re Y_c from column c, Im Y_c from column n + c

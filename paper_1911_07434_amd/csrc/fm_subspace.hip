@@ -137,39 +137,35 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
 
-  const int nchunk = (kdim + kSkChunk - 1) / kSkChunk;
-  const int velems = kSkChunk * n;  // <= 32 * 64 = 2048 -> at most 8 per thread
+  // Chunks whose SK-runs all lie inside kdim ("full") stream with every
+  // load unconditional: the prefetch of chunk c + 1 is clamped to the last
+  // full chunk (a repeat of it hits the cache), and V is read into
+  // registers before the R prefetch and written to LDS only after the
+  // chunk's MFMAs, so the wait for V never waits for the R prefetch behind
+  // it.  A ragged last chunk runs after the loop with per-element guards.
+  const int velems = kSkChunk * n;  // <= 16 * 16 NB (SK = 8) or 32 * 16 NB (SK = 16)
+  constexpr int JV = (kSkChunk * 16 * NB + 255) / 256;
   const gfloat2 *V = (const gfloat2 *)Bm;
-  float2 vst[8];
-  auto load_v = [&](int c) {
+  float2 vst[JV];
+  // V rows of chunk c (kSkChunk x n, row-major); elements past `lim` (rows
+  // past kdim) are read from a valid address and replaced by zero on store
+  auto load_v = [&](int c, int lim) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int e = tid + 256 * j;
-      const int m = c * kSkChunk + e / n;
-      vst[j] = make_float2(0.f, 0.f);
-      if (e < velems && m < kdim) vst[j] = V[(size_t)c * kSkChunk * n + e];
+    for (int j = 0; j < JV; ++j) {
+      const int e = min(tid + 256 * j, lim - 1);
+      vst[j] = V[(size_t)c * kSkChunk * n + e];
     }
   };
-  auto store_v = [&](int buf) {
+  auto store_v = [&](int buf, int lim) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < JV; ++j) {
       const int e = tid + 256 * j;
-      if (e < velems) vbuf[buf][e] = vst[j];
+      if (e < velems) vbuf[buf][e] = e < lim ? vst[j] : make_float2(0.f, 0.f);
     }
   };
-  // A chunk c: SK elements of this lane's row; columns past kdim read as zero
-  auto load_r = [&](float2 (&a)[SK], int c) {
-    const int m0 = c * kSkChunk + SK * h;
-    if (m0 + SK <= kdim) {
+  auto load_r_full = [&](float2 (&a)[SK], int c) {
 #pragma unroll
-      for (int s = 0; s < SK; ++s) a[s] = pr[c * kSkChunk + s];
-    } else {
-#pragma unroll
-      for (int s = 0; s < SK; ++s) {
-        a[s] = make_float2(0.f, 0.f);
-        if (m0 + s < kdim) a[s] = pr[c * kSkChunk + s];
-      }
-    }
+    for (int s = 0; s < SK; ++s) a[s] = pr[c * kSkChunk + s];
   };
   auto compute = [&](const float2 (&a)[SK], const float2 *vb) {
 #pragma unroll
@@ -185,30 +181,45 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
     }
   };
 
+  const int nfull = kdim / kSkChunk;
   float2 a0[SK], a1[SK];
-  load_v(0);
-  store_v(0);
-  load_r(a0, 0);
-  __syncthreads();
-  for (int c = 0; c < nchunk; c += 2) {
-    // chunk c from (a0, vbuf[0]); chunk c+1 from (a1, vbuf[1])
-    const bool has1 = c + 1 < nchunk;
-    if (has1) {
-      load_v(c + 1);
-      load_r(a1, c + 1);
+  if (nfull > 0) {
+    load_v(0, velems);
+    load_r_full(a0, 0);
+    store_v(0, velems);
+    __syncthreads();
+    for (int c = 0; c < nfull; c += 2) {
+      // chunk c from (a0, vbuf[0]); chunk c+1 from (a1, vbuf[1])
+      const int c1 = min(c + 1, nfull - 1);
+      load_v(c1, velems);
+      load_r_full(a1, c1);
+      compute(a0, vbuf[0]);
+      store_v(1, velems);
+      __syncthreads();
+      if (c + 1 >= nfull) break;
+      const int c2 = min(c + 2, nfull - 1);
+      load_v(c2, velems);
+      load_r_full(a0, c2);
+      compute(a1, vbuf[1]);
+      store_v(0, velems);
+      __syncthreads();
     }
+  }
+  if (nfull * kSkChunk < kdim) {
+    // ragged last chunk: columns past kdim read as zero, V rows past kdim
+    // are zero in LDS; vbuf[0] is free (every wave passed the last barrier)
+    const int c = nfull;
+    const int lim = (kdim - c * kSkChunk) * n;
+    load_v(c, lim);
+    const int m0 = c * kSkChunk + SK * h;
+#pragma unroll
+    for (int s = 0; s < SK; ++s) {
+      a0[s] = make_float2(0.f, 0.f);
+      if (m0 + s < kdim) a0[s] = pr[c * kSkChunk + s];
+    }
+    store_v(0, lim);
+    __syncthreads();
     compute(a0, vbuf[0]);
-    if (has1) store_v(1);
-    __syncthreads();
-    if (!has1) break;
-    const bool has2 = c + 2 < nchunk;
-    if (has2) {
-      load_v(c + 2);
-      load_r(a0, c + 2);
-    }
-    compute(a1, vbuf[1]);
-    if (has2) store_v(0);
-    __syncthreads();
   }
   if (scale != 1.f) {
 #pragma unroll
