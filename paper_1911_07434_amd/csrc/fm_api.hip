@@ -844,22 +844,20 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     for (int i : order) {
       if (frames[i].method == FM_METHOD_PROJECT_X || frames[i].method == FM_METHOD_SAMPLE_X)
         continue;  // forms no R
-      const int e = fm::cov_edge(prec);
-      const int nt = (frames[i].M + e - 1) / e;
       if (ctx->knob[FM_KNOB_COV_SCHEDULE][cov_bucket(frames[i].M)] == 0) {
         // the whole frame onto the least-loaded XCD
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[x] += (double)nt * (nt + 1) / 2 * frames[i].T;
-        for (int ti = 0; ti < nt; ++ti)
-          for (int tj = 0; tj <= ti; ++tj) q[x].push_back({i, ti, tj, 0});
+        fm::cov_each_unit(frames[i].M, prec, [&](int a, int b) {
+          load[x] += frames[i].T;
+          q[x].push_back({i, a, b, 0});
+        });
       } else {
-        // each tile onto the least-loaded XCD
-        for (int ti = 0; ti < nt; ++ti)
-          for (int tj = 0; tj <= ti; ++tj) {
-            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            load[x] += frames[i].T;
-            q[x].push_back({i, ti, tj, 0});
-          }
+        // each unit onto the least-loaded XCD
+        fm::cov_each_unit(frames[i].M, prec, [&](int a, int b) {
+          const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+          load[x] += frames[i].T;
+          q[x].push_back({i, a, b, 0});
+        });
       }
     }
     std::vector<size_t> pos(kXcd, 0);

@@ -79,7 +79,8 @@ struct Item {
 constexpr int kGramRows = 128;     // rows of the sketch per Gram partial
 constexpr int kSmallSlots = 8;     // npad^2 complex128 matrices per frame
 constexpr int kCovTile = 128;      // 16-bit covariance: tile edge (complex entries)
-constexpr int kCovBlock = 64;      // FP32 covariance: block edge, one wave per block
+constexpr int kCovBlock = 64;      // FP32 covariance: rows of a wave block (one wave per block)
+constexpr int kCovCols = 32;       // FP32 covariance: columns of a wave block
 constexpr int kSketchRows = 128;   // rows of R per sketch workgroup
 constexpr int kApplyRows = 64;     // rows per apply / gather workgroup
 constexpr int kSpecChunk = 64;     // lags staged in LDS per step of the polynomial pass
@@ -193,15 +194,32 @@ hipError_t launch_refine(const FrameDev &single, const FrameDev *frames, const I
 hipError_t launch_peaks(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, hipStream_t s);
 
-// covariance work unit edge for a precision: the FP32 kernel runs one wave per
-// 64x64 block, the 16-bit kernel one workgroup per 128x128 tile
+// Covariance work units of one frame.  16-bit: one workgroup per 128x128
+// tile (ti, tj <= ti) of the lower triangle.  FP32: one wave per 64x32 block
+// (bi, bj) with bj <= 2 bi + 1 (the blocks of 64-row block bi that reach the
+// diagonal), bj < ceil(M / 32).
 inline int cov_edge(fm_prec prec) { return prec == FM_FP32 ? kCovBlock : kCovTile; }
 
-// number of covariance workgroups one frame needs (lower-triangle units)
+// units a single-frame launch covers (FP32: whole block rows; units whose
+// columns start past M exit at once)
 inline int cov_units(int M, fm_prec prec) {
   const int e = cov_edge(prec);
   const int nt = (M + e - 1) / e;
-  return nt * (nt + 1) / 2;
+  return prec == FM_FP32 ? nt * (nt + 1) : nt * (nt + 1) / 2;
+}
+
+// every non-empty unit (a, b) of a frame, in row order
+template <class F>
+inline void cov_each_unit(int M, fm_prec prec, F &&fn) {
+  const int e = cov_edge(prec);
+  const int nt = (M + e - 1) / e;
+  for (int a = 0; a < nt; ++a) {
+    if (prec == FM_FP32) {
+      for (int b = 0; b <= 2 * a + 1 && b * kCovCols < M; ++b) fn(a, b);
+    } else {
+      for (int b = 0; b <= a; ++b) fn(a, b);
+    }
+  }
 }
 
 }  // namespace fm

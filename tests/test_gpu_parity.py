@@ -79,6 +79,7 @@ def test_covariance_gaussian(ctx, M, T):
     Rg = R.cpu().numpy()
     Ro = oracle.covariance(fr.X, threads=oracle.default_threads())
     err = np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)
+    say(f"  relative Frobenius error {err:.3g}")
     assert err <= 1e-6
     assert np.array_equal(Rg, Rg.conj().T)
     assert np.all(np.diag(Rg).imag == 0)
