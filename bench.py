@@ -44,6 +44,23 @@ def cov_flops(M, T):
     return 8.0 * M * (M + 1) / 2.0 * T
 
 
+def cov_mfma_flops(M, T, prec):
+    """Flops the covariance kernel actually issues on the matrix cores (the
+    blocks it computes in full, diagonal ones included): the FP32 kernel
+    computes every 32x32 block of the lower triangle with three real products
+    per complex product (6 flops per entry and snapshot); the 16-bit kernel
+    computes 32x32 blocks of 128x128 tiles (a diagonal tile skips one of its
+    four 64x64 quarters) with two real products per complex product (8 flops
+    per entry and snapshot), three times that with split operands."""
+    if prec == "fp32":
+        nb = (M + 31) // 32
+        return nb * (nb + 1) // 2 * 1024 * T * 6.0
+    nt = (M + 127) // 128
+    tiles = nt * (nt + 1) // 2
+    subs = (tiles - nt) * 16 + nt * 12
+    return subs * 1024 * T * (24.0 if prec.endswith("x3") else 8.0)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -345,12 +362,17 @@ def main():
     traffic = pmc_traffic(B, args.prec)
     peak = PEAK_FP32_MFMA_TFLOPS if args.prec == "fp32" else PEAK_F16_MFMA_TFLOPS
     kname = "cov_fp32_kernel" if args.prec == "fp32" else "cov16_kernel"
+    hw = B * cov_mfma_flops(M, T, args.prec)
     roofline = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 2),
                 "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4),
                 "traffic": traffic,
                 "launch_ms": round(cov_ms, 4),
-                "algorithmic_flops_per_launch": B * cov_flops(M, T)}
+                "algorithmic_flops_per_launch": B * cov_flops(M, T),
+                # what the matrix cores execute: the FP32 kernel's three-product
+                # complex multiply issues fewer flops than the algorithmic count
+                "mfma_flops_per_launch": hw,
+                "mfma_busy_frac": round(hw / (cov_ms * 1e-3) / 1e12 / peak, 4)}
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "frames/s", "n_gpus": 1,
@@ -398,11 +420,9 @@ def main():
                             "stage_ms_per_step": {k: round(v, 4) for k, v in sm.items()},
                             "covariance_tflops": round(am, 1),
                             "covariance_frac_of_16bit_peak": round(am / PEAK_F16_MFMA_TFLOPS, 4)}
-            if pname.endswith("x3"):
-                # three 16-bit products per complex product: matrix-core work
-                # is three times the algorithmic count
-                mixed[pname]["covariance_mfma_frac_of_16bit_peak"] = round(
-                    3 * am / PEAK_F16_MFMA_TFLOPS, 4)
+            mixed[pname]["covariance_mfma_busy_frac"] = round(
+                B * cov_mfma_flops(M, T, pname) / (sm["covariance"] * 1e-3) / 1e12
+                / PEAK_F16_MFMA_TFLOPS, 4)
             dP = max(float(np.max(np.abs(10 * np.log10(
                 frames2[i].P.double().cpu().numpy() / P_main[i])))) for i in range(n_chk))
             mixed[pname]["max_abs_dP_dB_vs_main_step"] = float(f"{dP:.3g}")
