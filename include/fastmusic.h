@@ -154,7 +154,10 @@ size_t fm_workspace_bytes(int M, int n, int K, int L);
  *   R   complex64 [M][ldr] (ldr >= M); every entry is written; R is exactly
  *       Hermitian (R[j][i] == conj(R[i][j]) bit for bit, imaginary diagonal 0)
  *   prec operand precision (accumulation FP32; the 1/T scale is applied in
- *       FP32 after accumulation)
+ *       FP32 after accumulation).  FM_FP32 forms each complex product with
+ *       three real products (Gauss: (a+b)c, a(c+d), b(c-d)), whose FP32
+ *       rounding stays at FP32 level; integer-valued snapshots with exactly
+ *       representable partial sums give exact results at every precision.
  * Requires M >= 1, T >= 1.  No workspace. */
 fm_status fm_covariance(fm_ctx *ctx, void *stream, const void *X, int M, int T,
                         int64_t ldx, void *R, int64_t ldr, fm_prec prec);
