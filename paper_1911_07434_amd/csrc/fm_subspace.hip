@@ -93,11 +93,11 @@ __global__ __launch_bounds__(256) void omega_kernel(FrameDev single, const Frame
 // sketch: Y = R V on FP32 MFMA.  One wave = 32 rows of R, all 2n real output
 // columns (n real parts, then n imaginary parts) in NB blocks of 32:
 //   Re Y = Rr Vr - Ri Vi,  Im Y = Rr Vi + Ri Vr
-// R streams in chunks of 32 columns: each lane owns 16 consecutive elements
-// of its row (half-wave h covers columns 16h..16h+15 of the chunk), prefetched
-// one chunk ahead in ping-pong registers; the chunk of V (32 x n) is staged
-// once per workgroup in double-buffered LDS.  MFMA step s pairs column s of
-// the first half with column 16+s of the second.
+// R streams in chunks of 32 columns: each lane owns 16 elements of its row
+// (pairs of columns, the two half-waves interleaved: lane h holds columns
+// 4j + 2h and 4j + 2h + 1), prefetched one chunk ahead in ping-pong
+// registers; the chunk of V (32 x n) is staged once per workgroup in
+// double-buffered LDS.  MFMA step s pairs the s-th column of each half.
 // ---------------------------------------------------------------------------
 constexpr int kSkChunkMax = 32;
 static_assert(kSketchRows == kGramRows, "a sketch workgroup covers one Gram chunk");
@@ -121,7 +121,10 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
   const int r = lane & 31, h = lane >> 5;
   const int M = f.M, n = f.n;
   const int row = min(i0 + r, M - 1);
-  const gfloat2 *pr = (const gfloat2 *)(Am + (size_t)row * lda + SK * h);
+  // element s of a lane's chunk run is column 4 (s / 2) + 2 h + s % 2 of the
+  // chunk: the two half-waves read neighbouring 16-byte pieces, so each load
+  // instruction touches one cache line per row, not two
+  const gfloat2 *pr = (const gfloat2 *)(Am + (size_t)row * lda + 2 * h);
   int col[NB], part[NB];
   bool okc[NB];
 #pragma unroll
@@ -165,14 +168,15 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
   };
   auto load_r_full = [&](float2 (&a)[SK], int c) {
 #pragma unroll
-    for (int s = 0; s < SK; ++s) a[s] = pr[c * kSkChunk + s];
+    for (int s = 0; s < SK; ++s) a[s] = pr[c * kSkChunk + 4 * (s >> 1) + (s & 1)];
   };
   auto compute = [&](const float2 (&a)[SK], const float2 *vb) {
 #pragma unroll
     for (int s = 0; s < SK; ++s) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const float2 v = okc[b] ? vb[(SK * h + s) * n + col[b]] : make_float2(0.f, 0.f);
+        const int m = 4 * (s >> 1) + 2 * h + (s & 1);
+        const float2 v = okc[b] ? vb[m * n + col[b]] : make_float2(0.f, 0.f);
         const float bre = part[b] == 0 ? v.x : v.y;
         const float bim = part[b] == 0 ? -v.y : v.x;
         acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s].x, bre, acc[b], 0, 0, 0);
@@ -211,11 +215,11 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
     const int c = nfull;
     const int lim = (kdim - c * kSkChunk) * n;
     load_v(c, lim);
-    const int m0 = c * kSkChunk + SK * h;
 #pragma unroll
     for (int s = 0; s < SK; ++s) {
+      const int mo = 4 * (s >> 1) + (s & 1);
       a0[s] = make_float2(0.f, 0.f);
-      if (m0 + s < kdim) a0[s] = pr[c * kSkChunk + s];
+      if (c * kSkChunk + mo + 2 * h < kdim) a0[s] = pr[c * kSkChunk + mo];
     }
     store_v(0, lim);
     __syncthreads();
