@@ -602,17 +602,28 @@ __device__ inline int rr_index(int pos, int round, int np) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (np - 1);
 }
 
-// Block reduction of one double per thread in a fixed tree order.
-__device__ double block_sum(double v, double *red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
+// Block sums of two doubles per thread in a fixed order: an xor butterfly
+// inside each wave (both partners add the same two operands, so every lane
+// ends with the same bits), then the wave sums in wave order.  Two barriers.
+__device__ void block_sum2(double &a, double &b, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
   }
-  const double r = red[0];
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * w] = a;
+    red[2 * w + 1] = b;
+  }
   __syncthreads();
-  return r;
+  a = 0.0;
+  b = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    a += red[2 * i];
+    b += red[2 * i + 1];
+  }
+  __syncthreads();  // red is reused by the next call
 }
 
 // Cyclic Jacobi with round-robin (parallel) ordering on an np x np Hermitian
@@ -629,8 +640,7 @@ __device__ int jacobi_eigh(double2 *A, double2 *V, int np, Rot *rot, double *red
       tot += a2;
       if (e / np != e % np) off += a2;
     }
-    off = block_sum(off, red);
-    tot = block_sum(tot, red);
+    block_sum2(off, tot, red);
     if (off == 0.0 || off <= 1e-30 * tot) return sweep;
     if (sweep == kMaxSweeps) return -1;
     for (int round = 0; round < np - 1; ++round) {
@@ -737,8 +747,16 @@ __device__ void sort_desc(const double2 *A, int np, int n, int *perm, double *w)
 template <int NMAX>
 struct SmallLds {
   static constexpr int kMat = NMAX > 0 ? NMAX * NMAX : 1;
+  // the final step's products Gc, P, Z stay in LDS for n <= 16 (wider
+  // classes keep them in global workspace slots, so that several
+  // workgroups still share a CU)
+  static constexpr bool kProdLds = NMAX > 0 && NMAX <= 16;
+  static constexpr int kProd = kProdLds ? NMAX * NMAX : 1;
   double2 A[kMat];
   double2 V[kMat];
+  double2 Gc[kProd];
+  double2 P[kProd];
+  double2 Z[kProd];
   Rot rot[NMAX > 0 ? NMAX / 2 : kMaxN / 2];
   double red[256];
   double w[kMaxN];
@@ -876,7 +894,8 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
   // ---- final: core -> P, H = P^H Gc P -> W, sigma; T_f = P W_K sigma^-1/2 ----
   const bool sample = f.method == FM_METHOD_SAMPLE || f.method == FM_METHOD_SAMPLE_X;
   // Gc (sum of partials, symmetrised) parked in its slot
-  double2 *Gc = slot(f, kSlotGc);
+  constexpr bool kProdLds = SmallLds<NMAX>::kProdLds;
+  double2 *Gc = kProdLds ? S.Gc : slot(f, kSlotGc);
   for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
     const int i = e / np, j = e % np;
     double2 v = make_double2(0.0, 0.0);
@@ -907,7 +926,7 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
   const int r1 = S.rank;
   const int rp = (r1 + 1) & ~1;
   // P = E_r diag(lambda^-1/2)   (n x r1, ld np)
-  double2 *P = slot(f, kSlotP);
+  double2 *P = kProdLds ? S.P : slot(f, kSlotP);
   for (int e = threadIdx.x; e < n * np; e += blockDim.x) {
     const int i = e / np, k = e % np;
     double2 v = make_double2(0.0, 0.0);
@@ -920,7 +939,7 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
   }
   __syncthreads();
   // Z = Gc P  (n x r1)
-  double2 *Z = slot(f, kSlotZ);
+  double2 *Z = kProdLds ? S.Z : slot(f, kSlotZ);
   for (int e = threadIdx.x; e < n * r1; e += blockDim.x) {
     const int i = e / r1, k = e % r1;
     double2 acc = make_double2(0.0, 0.0);
