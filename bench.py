@@ -123,6 +123,59 @@ def serve_legs(ctx, fm, torch, seconds, seed):
     return res
 
 
+def large_leg(fm, torch, ctx, stream, seed, n_frames=8, steps=3):
+    """The large-array workload: M = 4096, T = 8192, K = 16 as eight pairs
+    0.5 deg apart, SNR 0 dB, Method 2 with l = 24 and q = 2, 36001-angle grid
+    (0.005 deg), n_frames frames per plan, at every precision; frames/s,
+    stage times, the covariance rate and each precision's largest spectrum
+    difference against the FP32 path on the same frames."""
+    import fmsynth
+    from paper_1911_07434_amd.frames import DeviceFrame, FrameSpec
+    M4, T4, K4, l4, q4, L4 = 4096, 8192, 16, 24, 2, 36001
+    th0, dth, _ = fmsynth.grid(L4)
+    X, _ = fmsynth.make_batch_device(M4, T4, K4, 0.0, n_frames, seed, pairs=0.5)
+    Om = fmsynth.make_omega_device(M4, l4, n_frames, seed)
+    torch.cuda.synchronize()
+    spec = FrameSpec(M=M4, T=T4, K=K4, n=l4, q=q4, L=L4, theta0_deg=th0, dtheta_deg=dth)
+    frames = [DeviceFrame(spec, X=X[i], rnd=Om[i]) for i in range(n_frames)]
+    names = ("covariance", "subspace", "pseudospectrum", "peaks")
+    out = {"workload": f"M={M4} T={T4} K={K4} (pairs 0.5 deg apart) l={l4} q={q4} L={L4} "
+                       f"SNR=0dB, {n_frames} frames per plan"}
+    P_ref = None
+    for pname, prec in (("fp32", fm.FM_FP32), ("fp16", fm.FM_FP16), ("bf16", fm.FM_BF16),
+                        ("fp16x3", fm.FM_FP16X3), ("bf16x3", fm.FM_BF16X3)):
+        plan = fm.Plan(ctx, [d.descriptor() for d in frames], prec=prec)
+        with torch.cuda.stream(stream):
+            for st in (plan.covariance, plan.subspace, plan.pseudospectrum, plan.peaks):
+                st(stream)
+            torch.cuda.synchronize()
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+            for e in ev:
+                e[0].record(stream)
+                for i, st in enumerate((plan.covariance, plan.subspace, plan.pseudospectrum,
+                                        plan.peaks)):
+                    st(stream)
+                    e[i + 1].record(stream)
+            torch.cuda.synchronize()
+        sm = {n: float(np.median([e[i].elapsed_time(e[i + 1]) for e in ev]))
+              for i, n in enumerate(names)}
+        step_ms = float(np.median([e[0].elapsed_time(e[4]) for e in ev]))
+        P = [frames[i].P.double().cpu().numpy() for i in range(n_frames)]
+        rec = {"frames_per_s": round(n_frames / (step_ms * 1e-3), 1),
+               "stage_ms_per_step": {k: round(v, 3) for k, v in sm.items()},
+               "covariance_tflops": round(n_frames * cov_flops(M4, T4) / (sm["covariance"] * 1e-3)
+                                          / 1e12, 1)}
+        if P_ref is None:
+            P_ref = P
+        else:
+            dP = max(float(np.max(np.abs(10 * np.log10(a / b)))) for a, b in zip(P, P_ref))
+            rec["max_abs_dP_dB_vs_fp32"] = float(f"{dP:.3g}")
+        out[pname] = rec
+        log(f"large {pname}: {rec}")
+        plan.close()
+    return out
+
+
 def uneven_leg(fm, torch, stream, seed, steps, tune_cache=None):
     """The uneven-batch workload: 512 frames with M from {256, 512, 1024,
     2048}, T ~ U[M/2, 2M], K ~ U[1, 16], SNR ~ U[-5, 20] dB, Method 2 with
@@ -248,10 +301,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="time only the main step (for profiler runs); same as --legs ''")
-    ap.add_argument("--legs", default="compare,uneven,serve",
+    ap.add_argument("--legs", default="compare,large,uneven,serve",
                     help="extra legs after the main step: compare (mixed precision, Method 1, "
-                         "standard MUSIC, latency alone), uneven (512-frame uneven batch), "
-                         "serve (Poisson serving trace)")
+                         "standard MUSIC, latency alone), large (M=4096 T=8192 frames at "
+                         "every precision), uneven (512-frame uneven batch), serve (Poisson "
+                         "serving trace)")
     ap.add_argument("--prec", choices=("fp32", "fp16", "bf16", "fp16x3", "bf16x3"),
                     default="fp32",
                     help="covariance operand precision of the main timed step")
@@ -612,6 +666,10 @@ def main():
         }
         out["frame_latency_ms_alone"] = {"p50": round(float(np.percentile(lat, 50)), 3),
                                          "p99": round(float(np.percentile(lat, 99)), 3)}
+
+    # ---- large frames (M = 4096, T = 8192) at every precision -------------
+    if "large" in legs:
+        out["large_frames"] = large_leg(fm, torch, ctx, stream, args.seed + 11)
 
     # ---- uneven batch in one graph launch, built-in vs autotuned variants ---
     if "uneven" in legs and args.uneven_steps > 0:

@@ -164,19 +164,25 @@ def uneven_batch(n: int, seed: int, Ms=(256, 512, 1024, 2048), K_range=(1, 16),
 
 
 def make_batch_device(M: int, T: int, K: int, snr_db: float, n: int, seed: int, *,
-                      angle_range=(-75.0, 75.0), min_sep: float = 1.0, device="cuda"):
+                      angle_range=(-75.0, 75.0), min_sep: float = 1.0, device="cuda",
+                      pairs: float | None = None, pair_center_sep: float = 2.0):
     """n frames of the same shape generated on the GPU (for throughput runs).
 
     Same signal model as make_frame (angles drawn on the host with the same
-    rule, sources and noise drawn with a seeded torch generator on the
-    device).  Returns (X complex64 (n, M, T) on the device, angles (n, K)).
+    rule -- pairs `pairs` degrees apart when given -- sources and noise drawn
+    with a seeded torch generator on the device).  Returns (X complex64
+    (n, M, T) on the device, angles (n, K)).
     """
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
     rng = _rng(seed, 5)
-    th = np.stack([draw_angles(rng, K, angle_range[0], angle_range[1], min_sep)
-                   for _ in range(n)])
+    if pairs is not None:
+        th = np.stack([draw_pairs(rng, K // 2, pairs, angle_range[0], angle_range[1],
+                                  pair_center_sep) for _ in range(n)])
+    else:
+        th = np.stack([draw_angles(rng, K, angle_range[0], angle_range[1], min_sep)
+                       for _ in range(n)])
     A = torch.from_numpy(np.stack([steering_matrix(M, t) for t in th]).astype(np.complex64))
     A = A.to(device)                                           # (n, M, K)
     S = torch.complex(torch.randn((n, K, T), generator=g, device=device),
