@@ -413,7 +413,9 @@ fm_status fm_plan_run(fm_plan *plan, void *stream, int use_graph);
  *                          (M <= 128, 256, 512, 1024, 2048, >= 4096).
  *                          0: all covariance tiles of a frame go to one XCD
  *                          (one L2 holds its snapshots); 1: the frame's tiles
- *                          are dealt one by one to the least-loaded XCD.
+ *                          are dealt one by one to the least-loaded XCD;
+ *                          2 (built-in default): 1 for FM_FP32 frames with
+ *                          M >= 2048, 0 otherwise.
  *   FM_KNOB_SPEC_ANGLES    bucket = ceil(K/8) - 1 (0..7).  Angles per
  *                          workgroup of the FP32 (polynomial) spectrum pass
  *                          of a group of frames of that bucket: 64, 128, or

@@ -12,7 +12,8 @@ with the same shapes installs them without timing (``apply``).
 
 Knobs and buckets:
   cov_schedule   bucket log2(M) - 7 in [0, 5]; 0 = a frame's covariance tiles
-                 on one XCD, 1 = tiles dealt one by one to the XCDs
+                 on one XCD, 1 = tiles dealt one by one to the XCDs (the
+                 built-in 2 picks per precision; tuning installs 0 or 1)
   spec_angles    bucket ceil(K/8) - 1 in [0, 7]; angles per workgroup of the
                  FP32 (polynomial) spectrum pass, which every plan runs (64,
                  128, 256 for buckets 0..3)

@@ -70,13 +70,13 @@ def _same(a, b):
 
 
 def test_knob_defaults_and_validation(ctx):
-    assert ctx.get_knob(fm.FM_KNOB_COV_SCHEDULE, 0) == 0
+    assert ctx.get_knob(fm.FM_KNOB_COV_SCHEDULE, 0) == 2        # per-precision built-in
     assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 3) == 128
     assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 7) == 64
     assert ctx.get_knob(fm.FM_KNOB_SPEC16_ANGLES, 0) == 256
     assert ctx.get_knob(fm.FM_KNOB_COV_SCHEDULE, 6) == -1      # no such bucket
     assert ctx.get_knob(7, 0) == -1
-    for knob, bucket, value in [(fm.FM_KNOB_COV_SCHEDULE, 0, 2), (fm.FM_KNOB_SPEC_ANGLES, 4, 256),
+    for knob, bucket, value in [(fm.FM_KNOB_COV_SCHEDULE, 0, 3), (fm.FM_KNOB_SPEC_ANGLES, 4, 256),
                                 (fm.FM_KNOB_SPEC16_ANGLES, 0, 96), (fm.FM_KNOB_SPEC_ANGLES, 8, 64),
                                 (3, 0, 0)]:
         with pytest.raises(fm.FmError) as e:
