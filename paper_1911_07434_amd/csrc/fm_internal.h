@@ -12,8 +12,10 @@
 // pointers (global_load instead of flat_load); host passes see a plain type.
 #if defined(__HIP_DEVICE_COMPILE__)
 #define FM_GLOBAL __attribute__((address_space(1)))
+#define FM_LDS __attribute__((address_space(3)))
 #else
 #define FM_GLOBAL
+#define FM_LDS
 #endif
 
 namespace fm {

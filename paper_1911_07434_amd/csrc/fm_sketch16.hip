@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void sketch16_kernel(FrameDev single, const Fr
 
   // store Y (unscaled), Re Y_c from column c, Im Y_c from column n + c
   const float inv = 1.f / (sR * sV);
-  float *Yf = reinterpret_cast<float *>(f.Y);
+  FM_GLOBAL float *Yf = (FM_GLOBAL float *)f.Y;   // global stores (a flat one also holds up LDS waits)
   float *yt = reinterpret_cast<float *>(bsm);   // [128][n] complex tile for the Gram step
   const int gmode = round < 0 ? -1 : (round < f.q ? kGramSelf : kGramFinal);
 #pragma unroll
@@ -264,9 +264,11 @@ __global__ __launch_bounds__(256) void sketch16_kernel(FrameDev single, const Fr
   const int m0 = blk * kGramRows;
   const int rows = min(M, m0 + kGramRows) - m0;
   const float2 *Yt = reinterpret_cast<const float2 *>(yt);
-  gram_rows(Yt, Yt, f.part + (size_t)(blk * 2 + (gmode == kGramSelf ? 0 : 1)) * n * n, n, rows);
+  const FM_LDS float2 *Yl = (const FM_LDS float2 *)Yt;
+  gram_rows(Yl, Yl, f.part + (size_t)(blk * 2 + (gmode == kGramSelf ? 0 : 1)) * n * n, n, rows);
   if (gmode == kGramFinal)
-    gram_rows(f.V + (size_t)m0 * n, Yt, f.part + (size_t)(blk * 2) * n * n, n, rows);
+    gram_rows((const FM_GLOBAL float2 *)(f.V + (size_t)m0 * n), Yl,
+              f.part + (size_t)(blk * 2) * n * n, n, rows);
 }
 
 template <int NB>

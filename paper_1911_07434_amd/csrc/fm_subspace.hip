@@ -103,6 +103,7 @@ constexpr int kSkChunkMax = 32;
 static_assert(kSketchRows == kGramRows, "a sketch workgroup covers one Gram chunk");
 static_assert(kSkChunkMax * kMaxL * 2 >= kSketchRows * 32, "Y tile of n <= 32 fits the V buffers");
 typedef FM_GLOBAL const float2 gfloat2;
+typedef FM_GLOBAL const double2 gdouble2;
 
 // SK = elements of its row each lane holds per chunk (chunk = 2 SK columns);
 // wide column classes use SK = 8 to stay within the register file
@@ -231,7 +232,7 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[b][v] *= scale;
   }
-  float *Yf = reinterpret_cast<float *>(f.Y);
+  FM_GLOBAL float *Yf = (FM_GLOBAL float *)f.Y;   // global stores (a flat one also holds up LDS waits)
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     if (!okc[b]) continue;
@@ -261,10 +262,12 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
     const int m0 = chunk * kGramRows;
     const int rows = min(M, m0 + kGramRows) - m0;
     const float2 *Yt = reinterpret_cast<const float2 *>(yt);
-    gram_rows(Yt, Yt, f.part + (size_t)(chunk * 2 + (gmode == kGramSelf ? 0 : 1)) * n * n, n,
+    const FM_LDS float2 *Yl = (const FM_LDS float2 *)Yt;
+    gram_rows(Yl, Yl, f.part + (size_t)(chunk * 2 + (gmode == kGramSelf ? 0 : 1)) * n * n, n,
               rows);
     if (gmode == kGramFinal)
-      gram_rows(f.V + (size_t)m0 * n, Yt, f.part + (size_t)(chunk * 2) * n * n, n, rows);
+      gram_rows((const FM_GLOBAL float2 *)(f.V + (size_t)m0 * n), Yl,
+                f.part + (size_t)(chunk * 2) * n * n, n, rows);
   }
 }
 
@@ -528,8 +531,13 @@ __global__ __launch_bounds__(256) void gather_kernel(FrameDev single, const Fram
 // block of entries.
 // ---------------------------------------------------------------------------
 template <int TB>
-__device__ __forceinline__ void gram_block(const float2 *A, const float2 *B, double2 *out,
+__device__ __forceinline__ void gram_block(const float2 *Ain, const float2 *Bin, double2 *outp,
                                            int n, int m0, int m1) {
+  // the operands and partials live in global workspace: global-address
+  // loads, so the compiler's waits count only these loads
+  const gfloat2 *A = (const gfloat2 *)Ain;
+  const gfloat2 *B = (const gfloat2 *)Bin;
+  FM_GLOBAL double2 *out = (FM_GLOBAL double2 *)outp;
   const int nbk = (n + TB - 1) / TB;
   for (int blk = threadIdx.x; blk < nbk * nbk; blk += blockDim.x) {
     const int a0 = (blk / nbk) * TB, b0 = (blk % nbk) * TB;
@@ -542,8 +550,10 @@ __device__ __forceinline__ void gram_block(const float2 *A, const float2 *B, dou
       float2 av[TB], bv[TB];
 #pragma unroll
       for (int x = 0; x < TB; ++x) {
-        av[x] = (a0 + x < n) ? A[(size_t)m * n + a0 + x] : make_float2(0.f, 0.f);
-        bv[x] = (b0 + x < n) ? B[(size_t)m * n + b0 + x] : make_float2(0.f, 0.f);
+        const float2 a = A[(size_t)m * n + min(a0 + x, n - 1)];
+        const float2 b = B[(size_t)m * n + min(b0 + x, n - 1)];
+        av[x] = (a0 + x < n) ? a : make_float2(0.f, 0.f);
+        bv[x] = (b0 + x < n) ? b : make_float2(0.f, 0.f);
       }
 #pragma unroll
       for (int x = 0; x < TB; ++x)
@@ -777,13 +787,14 @@ __device__ void load_herm(double2 *A, double2 *V, int np, int n, const double2 *
       double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
       if (part) {
         for (int c = 0; c < nchunk; ++c) {
-          const double2 *pc = part + (size_t)(c * 2 + which) * n * n;
+          const FM_GLOBAL double2 *pc =
+              (const FM_GLOBAL double2 *)(part + (size_t)(c * 2 + which) * n * n);
           a = cadd(a, pc[(size_t)i * n + j]);
           b = cadd(b, pc[(size_t)j * n + i]);
         }
       } else {
-        a = src[(size_t)i * np + j];
-        b = src[(size_t)j * np + i];
+        a = ((const FM_GLOBAL double2 *)src)[(size_t)i * np + j];
+        b = ((const FM_GLOBAL double2 *)src)[(size_t)j * np + i];
       }
       // (A + A^H) / 2
       v = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
@@ -902,7 +913,8 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
     if (i < n && j < n) {
       double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
       for (int c = 0; c < f.nchunk; ++c) {
-        const double2 *pc = f.part + (size_t)(c * 2 + 1) * n * n;
+        const FM_GLOBAL double2 *pc =
+            (const FM_GLOBAL double2 *)(f.part + (size_t)(c * 2 + 1) * n * n);
         a = cadd(a, pc[(size_t)i * n + j]);
         b = cadd(b, pc[(size_t)j * n + i]);
       }
@@ -1025,30 +1037,50 @@ __global__ __launch_bounds__(256) void apply_kernel(FrameDev single, const Frame
   const float2 *Y = f.Y;
   const int ncol = mode == kApplyV ? n : f.K;
   const bool staged = n * ncol <= kApplyTMax && n <= kMaxL;
+  // one output (row m, column c) per thread and pass; the two paths are
+  // separate loops so that each reads through its own address space (a
+  // select between LDS and global pointers would make every read a flat
+  // load with a full wait)
+  auto put = [&](int c, int m, double2 acc) {
+    if (mode == kApplyV) {
+      ((FM_GLOBAL float2 *)f.V)[(size_t)m * n + c] = make_float2((float)acc.x, (float)acc.y);
+    } else {
+      ((FM_GLOBAL double2 *)f.Us)[(size_t)c * M + m] = acc;
+      ((FM_GLOBAL float2 *)f.Uf)[(size_t)m * ncol + c] =
+          make_float2((float)acc.x, (float)acc.y);
+    }
+  };
+  auto mac = [](double2 &acc, float2 y, double2 t) {
+    acc.x = fma((double)y.x, t.x, acc.x);
+    acc.x = fma(-(double)y.y, t.y, acc.x);
+    acc.y = fma((double)y.x, t.y, acc.y);
+    acc.y = fma((double)y.y, t.x, acc.y);
+  };
   if (staged) {
-    for (int e = threadIdx.x; e < n * ncol; e += blockDim.x) ts[e] = Tm[e];
+    const gdouble2 *Tg = (const gdouble2 *)Tm;
+    const gfloat2 *Yg = (const gfloat2 *)Y;
+    for (int e = threadIdx.x; e < n * ncol; e += blockDim.x) ts[e] = Tg[e];
     for (int e = threadIdx.x; e < rows * n; e += blockDim.x) {
       const int m = e / n, j = e % n;
-      ys[j * kApplyRows + m] = Y[(size_t)(m0 + m) * n + j];
+      ys[j * kApplyRows + m] = Yg[(size_t)(m0 + m) * n + j];
     }
     __syncthreads();
-  }
-  for (int e = threadIdx.x; e < rows * ncol; e += blockDim.x) {
-    const int c = e / rows, ml = e % rows, m = m0 + ml;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int j = 0; j < n; ++j) {
-      const float2 y = staged ? ys[j * kApplyRows + ml] : Y[(size_t)m * n + j];
-      const double2 t = staged ? ts[j * ncol + c] : Tm[(size_t)j * ncol + c];
-      acc.x = fma((double)y.x, t.x, acc.x);
-      acc.x = fma(-(double)y.y, t.y, acc.x);
-      acc.y = fma((double)y.x, t.y, acc.y);
-      acc.y = fma((double)y.y, t.x, acc.y);
+    for (int e = threadIdx.x; e < rows * ncol; e += blockDim.x) {
+      const int c = e / rows, ml = e % rows;
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+      for (int j = 0; j < n; ++j) mac(acc, ys[j * kApplyRows + ml], ts[j * ncol + c]);
+      put(c, m0 + ml, acc);
     }
-    if (mode == kApplyV) {
-      f.V[(size_t)m * n + c] = make_float2((float)acc.x, (float)acc.y);
-    } else {
-      f.Us[(size_t)c * M + m] = acc;
-      f.Uf[(size_t)m * ncol + c] = make_float2((float)acc.x, (float)acc.y);
+  } else {
+    const gdouble2 *Tg = (const gdouble2 *)Tm;
+    const gfloat2 *Yg = (const gfloat2 *)Y;
+    for (int e = threadIdx.x; e < rows * ncol; e += blockDim.x) {
+      const int c = e / rows, ml = e % rows, m = m0 + ml;
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+      for (int j = 0; j < n; ++j) mac(acc, Yg[(size_t)m * n + j], Tg[(size_t)j * ncol + c]);
+      put(c, m, acc);
     }
   }
 }
