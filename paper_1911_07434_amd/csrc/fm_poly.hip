@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
   }
   const int M = fp->M, K = fp->K;
   const double2 *Us = fp->Us;
-  float2 *hg = fp->hgrp + (size_t)rb * M * kPolyRows;
+  FM_GLOBAL float2 *hg = (FM_GLOBAL float2 *)(fp->hgrp + (size_t)rb * M * kPolyRows);
   const int slot = fp->hslot;
   const int tid = threadIdx.x;
   const int d0 = chunk * kAcorrLags;
@@ -74,21 +74,42 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
   float re[kAcL], im[kAcL];
 #pragma unroll
   for (int j = 0; j < kAcL; ++j) re[j] = im[j] = 0.f;
+  // column k of U_s in registers, fetched one column ahead with
+  // unconditional global loads (rows past M read row M - 1 and are staged as
+  // zero), then staged in LDS as FP32 (the values of its FP32 copy)
+  constexpr int kWa = kAcorrRows / kAcThreads;
+  constexpr int kWbN = kAcorrRows + kAcorrLags + kAcL;
+  constexpr int kWb = (kWbN + kAcThreads - 1) / kAcThreads;
+  const FM_GLOBAL double2 *Ug = (const FM_GLOBAL double2 *)Us;
+  double2 pa[kWa], pb[kWb];
+  auto fetch = [&](int k) {
+    const FM_GLOBAL double2 *u = Ug + (size_t)k * M;
+#pragma unroll
+    for (int i = 0; i < kWa; ++i) pa[i] = u[min(m0 + tid + kAcThreads * i, M - 1)];
+#pragma unroll
+    for (int i = 0; i < kWb; ++i) pb[i] = u[min(m0 + d0 + tid + kAcThreads * i, M - 1)];
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int i = 0; i < kWa; ++i) {
+      const int e = tid + kAcThreads * i;
+      const double2 v = m0 + e < M ? pa[i] : make_double2(0.0, 0.0);
+      wa[e] = make_float2((float)v.x, (float)v.y);
+    }
+#pragma unroll
+    for (int i = 0; i < kWb; ++i) {
+      const int e = tid + kAcThreads * i;
+      const double2 v = m0 + d0 + e < M ? pb[i] : make_double2(0.0, 0.0);
+      if (e < kWbN) wb[e] = make_float2((float)v.x, (float)v.y);
+    }
+  };
   if (m0 + d0 < M) {  // uniform: some lag of this workgroup reaches the block
+    fetch(0);
     for (int k = 0; k < K; ++k) {
-      const double2 *u = Us + (size_t)k * M;
       __syncthreads();  // the previous column has been read
-      // FP32 roundings of U_s (the values of its FP32 copy), read along the
-      // contiguous column k; rows past M are zero
-      for (int i = tid; i < kAcorrRows; i += kAcThreads) {
-        const double2 v = m0 + i < M ? u[m0 + i] : make_double2(0.0, 0.0);
-        wa[i] = make_float2((float)v.x, (float)v.y);
-      }
-      for (int i = tid; i < kAcorrRows + kAcorrLags + kAcL; i += kAcThreads) {
-        const double2 v = m0 + d0 + i < M ? u[m0 + d0 + i] : make_double2(0.0, 0.0);
-        wb[i] = make_float2((float)v.x, (float)v.y);
-      }
+      stage();
       __syncthreads();
+      fetch(min(k + 1, K - 1));
       // rows of this block used by the lane's first (longest) lag
       const int cnt = min(kAcorrRows, M - dl - m0);
       if (cnt > 0) {
@@ -165,7 +186,9 @@ __device__ __forceinline__ void poly_tile(const FrameDev &single, const FrameDev
   const int wave = tid >> 6;
   const int n = lane & 15, r = lane >> 4;
   const int M = g.M, L = g.L;
-  const float2 *hg = g.hgrp;
+  // global-address loads (a flat load would also count against the LDS
+  // waits of the MFMA loop and drain this prefetch every chunk)
+  const FM_GLOBAL float2 *hg = (const FM_GLOBAL float2 *)g.hgrp;
   const int first = tile * (64 * NNB) + wave * (16 * NNB);
   unsigned long long F[NNB];
 #pragma unroll
@@ -185,7 +208,8 @@ __device__ __forceinline__ void poly_tile(const FrameDev &single, const FrameDev
 #pragma unroll
     for (int j = 0; j < kChunkElems / 256; ++j) {
       const size_t e = base + tid + 256 * j;
-      stage[j] = e < total ? hg[e] : make_float2(0.f, 0.f);
+      const float2 v = hg[e < total ? e : total - 1];   // unconditional load
+      stage[j] = e < total ? v : make_float2(0.f, 0.f);
     }
   };
   auto store_chunk = [&](int buf) {
