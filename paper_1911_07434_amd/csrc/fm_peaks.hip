@@ -4,8 +4,8 @@
 // plateau reports its leftmost point; the K largest peaks are reported in
 // the total order (value descending, index ascending).
 //
-// One 1024-thread workgroup per spectrum.  Each thread marks the peaks of a
-// contiguous chunk; the candidates are compacted into LDS with a block scan;
+// One 1024-thread workgroup per spectrum.  Thread t marks the peaks among
+// l = t, t + 1024, ... (coalesced loads); the candidates are compacted into LDS with a block scan;
 // then K rounds each select the first candidate after the previous winner in
 // the total order with a wavefront shuffle reduction and a 16-entry LDS
 // reduction.  If a spectrum has more local maxima than the LDS list holds,
@@ -28,11 +28,15 @@ __device__ inline bool before(float av, int ai, float bv, int bi) {
   return av > bv || (av == bv && ai < bi);
 }
 
-__device__ inline bool is_peak(const float *P, int L, int l) {
-  const float v = P[l];
-  const bool left = (l == 0) || (v > P[l - 1]);
-  const bool right = (l == L - 1) || (v >= P[l + 1]);
-  return left && right;
+// l is a peak; l may lie past the end (then false).  The three loads are
+// unconditional (clamped), so the scan issues them without waiting on a branch.
+__device__ inline bool is_peak(const FM_GLOBAL float *P, int L, int l, float &v) {
+  const int c = min(l, L - 1);
+  v = P[c];
+  const float pl = P[max(c - 1, 0)], pr = P[min(c + 1, L - 1)];
+  const bool left = (c == 0) || (v > pl);
+  const bool right = (c == L - 1) || (v >= pr);
+  return l < L && left && right;
 }
 
 template <bool kBatched>
@@ -40,7 +44,7 @@ __global__ __launch_bounds__(kPeakThreads) void peaks_kernel(FrameDev single,
                                                             const FrameDev *frames,
                                                             const Item *items) {
   const FrameDev &f = kBatched ? frames[items[blockIdx.x].frame] : single;
-  const float *P = f.P;
+  const FM_GLOBAL float *P = (const FM_GLOBAL float *)f.P;
   const int L = f.L, K = f.K;
   __shared__ Cand list[kPeakCap];
   __shared__ int wcount[kPeakThreads / 64];
@@ -50,12 +54,19 @@ __global__ __launch_bounds__(kPeakThreads) void peaks_kernel(FrameDev single,
   __shared__ float prev_v;
   __shared__ int prev_i;
   __shared__ int found_s;
+  // the K <= kMaxK selections, written out once at the end (a global store
+  // before each round's barrier would make every round wait for it)
+  __shared__ int sel_i[kMaxK];
+  __shared__ float sel_v[kMaxK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int chunk = (L + kPeakThreads - 1) / kPeakThreads;
-  const int lo = min(L, tid * chunk), hi = min(L, lo + chunk);
+  // thread tid owns l = tid, tid + 1024, ... (coalesced across the wave)
+  const int per = (L + kPeakThreads - 1) / kPeakThreads;
   int mine = 0;
-  for (int l = lo; l < hi; ++l) mine += is_peak(P, L, l);
+  for (int j = 0; j < per; ++j) {
+    float v;
+    mine += is_peak(P, L, tid + j * kPeakThreads, v);
+  }
   // exclusive scan of the per-thread counts: wave scan, then wave offsets
   int incl = mine;
 #pragma unroll
@@ -82,8 +93,11 @@ __global__ __launch_bounds__(kPeakThreads) void peaks_kernel(FrameDev single,
   const bool in_lds = total <= kPeakCap;
   if (in_lds) {
     int pos = wcount[wave] + incl - mine;
-    for (int l = lo; l < hi; ++l)
-      if (is_peak(P, L, l)) list[pos++] = Cand{P[l], l};
+    for (int j = 0; j < per; ++j) {
+      const int l = tid + j * kPeakThreads;
+      float v;
+      if (is_peak(P, L, l, v)) list[pos++] = Cand{v, l};
+    }
   }
   __syncthreads();
 
@@ -102,9 +116,10 @@ __global__ __launch_bounds__(kPeakThreads) void peaks_kernel(FrameDev single,
         }
       }
     } else {
-      for (int l = lo; l < hi; ++l) {
-        if (!is_peak(P, L, l)) continue;
-        const float v = P[l];
+      for (int j = 0; j < per; ++j) {
+        const int l = tid + j * kPeakThreads;
+        float v;
+        if (!is_peak(P, L, l, v)) continue;
         if (before(pv, pi, v, l) && (bi < 0 || before(v, l, bv, bi))) {
           bv = v;
           bi = l;
@@ -133,13 +148,17 @@ __global__ __launch_bounds__(kPeakThreads) void peaks_kernel(FrameDev single,
           v = wv[w];
           i = wi[w];
         }
-      f.peak_idx[k] = i;
-      f.peak_val[k] = v;
+      sel_i[k] = i;
+      sel_v[k] = v;
       prev_v = v;
       prev_i = i;
       found_s = k + 1;
     }
     __syncthreads();
+  }
+  for (int k = tid; k < found_s; k += kPeakThreads) {
+    f.peak_idx[k] = sel_i[k];
+    f.peak_val[k] = sel_v[k];
   }
   if (tid == 0) {
     *f.n_found = found_s;

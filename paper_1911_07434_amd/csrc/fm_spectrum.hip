@@ -57,7 +57,7 @@ __device__ void den_fp64_wave(const FrameDev &f, const unsigned long long (&F)[k
   }
   for (int k0 = 0; k0 < K; k0 += kRefK) {
     const int kn = min(kRefK, K - k0);
-    const double2 *u0 = f.Us + (size_t)k0 * M;
+    const FM_GLOBAL double2 *u0 = (const FM_GLOBAL double2 *)(f.Us + (size_t)k0 * M);
     double2 acc[kRefAngles][kRefK];
     double2 a[kRefAngles];
 #pragma unroll
@@ -74,7 +74,10 @@ __device__ void den_fp64_wave(const FrameDev &f, const unsigned long long (&F)[k
         double2 u[kRefK];
 #pragma unroll
         for (int k = 0; k < kRefK; ++k)
-          u[k] = k < kn ? u0[(size_t)k * M + m] : make_double2(0.0, 0.0);
+        {
+          const double2 v = u0[(size_t)min(k, kn - 1) * M + m];   // unconditional load
+          u[k] = k < kn ? v : make_double2(0.0, 0.0);
+        }
 #pragma unroll
         for (int j = 0; j < kRefAngles; ++j)
 #pragma unroll
