@@ -37,12 +37,14 @@ __device__ __forceinline__ const FrameDev &spec_frame(const FrameDev &single,
 
 constexpr int kRefAngles = 4;  // angles per wave
 constexpr int kRefK = 4;       // sources per pass over the channels
+constexpr int kRefU = 4;       // 64-channel blocks fetched together
 
 // FP64 denominators of kRefAngles angles (phase frequencies F) by one wave.
 // Each lane walks every 64th channel with an FP64 phasor recurrence,
 // restarted exactly every 4096 channels (at most 64 steps per exact start,
-// error ~1e-14), and reads U_s straight from memory: the frame's waves share
-// it through the caches, and no wave waits for another.  The sources are
+// error ~1e-14), and reads U_s straight from memory, kRefU 64-channel blocks
+// at a time: the frame's waves share it through the caches, and no wave
+// waits for another.  The sources are
 // taken kRefK at a time, the angles all at once, so every U_s element loaded
 // serves kRefAngles angles.
 __device__ void den_fp64_wave(const FrameDev &f, const unsigned long long (&F)[kRefAngles],
@@ -55,42 +57,56 @@ __device__ void den_fp64_wave(const FrameDev &f, const unsigned long long (&F)[k
     proj[j] = 0.0;
     w[j] = phasor64(64, F[j]);
   }
+  const int mlast = M - 1;
   for (int k0 = 0; k0 < K; k0 += kRefK) {
     const int kn = min(kRefK, K - k0);
     const FM_GLOBAL double2 *u0 = (const FM_GLOBAL double2 *)(f.Us + (size_t)k0 * M);
+    // rows past the last source repeat it; their sums are dropped below
+    size_t row[kRefK];
+#pragma unroll
+    for (int k = 0; k < kRefK; ++k) row[k] = (size_t)min(k, kn - 1) * M;
     double2 acc[kRefAngles][kRefK];
     double2 a[kRefAngles];
 #pragma unroll
     for (int j = 0; j < kRefAngles; ++j)
 #pragma unroll
       for (int k = 0; k < kRefK; ++k) acc[j][k] = make_double2(0.0, 0.0);
-    for (int mc = 0; mc < M; mc += 64) {
-      const int m = mc + lane;
-      if ((mc & 4095) == 0) {
+    // kRefU channel blocks of 64 are fetched together (kRefU * kRefK loads in
+    // flight), then accumulated in channel order
+    for (int mg = 0; mg < M; mg += 64 * kRefU) {
+      double2 u[kRefU][kRefK];
 #pragma unroll
-        for (int j = 0; j < kRefAngles; ++j) a[j] = phasor64((unsigned long long)m, F[j]);
+      for (int b = 0; b < kRefU; ++b) {
+        const int mb = min(mg + 64 * b + lane, mlast);
+#pragma unroll
+        for (int k = 0; k < kRefK; ++k) u[b][k] = u0[row[k] + mb];
       }
-      if (m < M) {
-        double2 u[kRefK];
 #pragma unroll
-        for (int k = 0; k < kRefK; ++k)
-        {
-          const double2 v = u0[(size_t)min(k, kn - 1) * M + m];   // unconditional load
-          u[k] = k < kn ? v : make_double2(0.0, 0.0);
+      for (int b = 0; b < kRefU; ++b) {
+        const int mc = mg + 64 * b;
+        if (mc >= M) break;
+        const int m = mc + lane;
+        if (m > mlast) {
+#pragma unroll
+          for (int k = 0; k < kRefK; ++k) u[b][k] = make_double2(0.0, 0.0);
+        }
+        if ((mc & 4095) == 0) {
+#pragma unroll
+          for (int j = 0; j < kRefAngles; ++j) a[j] = phasor64((unsigned long long)m, F[j]);
         }
 #pragma unroll
         for (int j = 0; j < kRefAngles; ++j)
 #pragma unroll
           for (int k = 0; k < kRefK; ++k) {
             // conj(u) * a
-            acc[j][k].x = fma(u[k].x, a[j].x, fma(u[k].y, a[j].y, acc[j][k].x));
-            acc[j][k].y = fma(u[k].x, a[j].y, fma(-u[k].y, a[j].x, acc[j][k].y));
+            acc[j][k].x = fma(u[b][k].x, a[j].x, fma(u[b][k].y, a[j].y, acc[j][k].x));
+            acc[j][k].y = fma(u[b][k].x, a[j].y, fma(-u[b][k].y, a[j].x, acc[j][k].y));
           }
-      }
 #pragma unroll
-      for (int j = 0; j < kRefAngles; ++j)
-        a[j] = make_double2(fma(a[j].x, w[j].x, -(a[j].y * w[j].y)),
-                            fma(a[j].x, w[j].y, a[j].y * w[j].x));
+        for (int j = 0; j < kRefAngles; ++j)
+          a[j] = make_double2(fma(a[j].x, w[j].x, -(a[j].y * w[j].y)),
+                              fma(a[j].x, w[j].y, a[j].y * w[j].x));
+      }
     }
 #pragma unroll
     for (int j = 0; j < kRefAngles; ++j)
@@ -118,16 +134,21 @@ __global__ __launch_bounds__(256) void refine_kernel(FrameDev single, const Fram
   int part;
   const FrameDev &f = spec_frame<kBatched>(single, frames, items, part);
   const int lane = threadIdx.x & 63;
-  const int cnt = f.rlist[0];
+  const FM_GLOBAL int *rl = (const FM_GLOBAL int *)f.rlist;
+  const int cnt = rl[0];
   const double floor64 = (double)f.M * 1.1102230246251565e-16;  // M * 2^-53
   const int stride = kRefineGroups * 4 * kRefAngles;
   for (int e0 = (part * 4 + (threadIdx.x >> 6)) * kRefAngles; e0 < cnt; e0 += stride) {
     unsigned long long F[kRefAngles];
     int gl[kRefAngles];
+    // entries past the end repeat the last one (computed, never stored)
+    int r[kRefAngles];
+#pragma unroll
+    for (int j = 0; j < kRefAngles; ++j) r[j] = rl[1 + min(e0 + j, cnt - 1)];
 #pragma unroll
     for (int j = 0; j < kRefAngles; ++j) {
-      gl[j] = e0 + j < cnt ? f.rlist[1 + e0 + j] : -1;
-      F[j] = gl[j] >= 0 ? turn_freq(f.theta0, f.dtheta, gl[j]) : 0ull;
+      gl[j] = e0 + j < cnt ? r[j] : -1;
+      F[j] = turn_freq(f.theta0, f.dtheta, r[j]);
     }
     double d[kRefAngles];
     den_fp64_wave(f, F, lane, d);
