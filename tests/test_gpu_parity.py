@@ -164,6 +164,28 @@ def test_spectrum_single_source_pole_and_dirichlet(ctx, prec):
     assert np.isfinite(Pg[l0]) and Pg[l0] > 1e6
 
 
+# the FP64 recompute of main-lobe angles with ragged channel counts (a
+# partial 64-channel block, a partial group of four blocks) and a partial
+# group of four sources: a steering vector in the subspace puts a pole on the
+# grid, so its lobe is listed for the recompute
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("M,K", [(300, 6), (1000, 9), (70, 5)])
+def test_spectrum_refine_ragged(ctx, M, K, prec):
+    L = 4097
+    th0, dth = -80.0, 160.0 / (L - 1)
+    l0 = 2345
+    a0 = fmsynth.steering_matrix(M, [th0 + l0 * dth])[:, 0] / np.sqrt(M)
+    rng = np.random.default_rng(M * K)
+    G = rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))
+    G[:, 0] = a0
+    Q, _ = np.linalg.qr(G)
+    Pg, Po, _ = _spectrum_case(ctx, np.ascontiguousarray(Q.T), th0, dth, L, prec)
+    assert int(np.argmax(Pg)) == l0
+    ok = np.abs(np.arange(L) - l0) > 0
+    assert db_err(Pg[ok], Po[ok]) <= DB_FP32
+    assert np.isfinite(Pg[l0]) and Pg[l0] > 1e6
+
+
 # ----------------------------------------------------------------------------
 # stage 4: peaks on identical float32 spectra (bit-exact)
 # ----------------------------------------------------------------------------
