@@ -179,7 +179,7 @@ hipError_t launch_spectrum16(const FrameDev &single, const FrameDev *frames, con
                              int n_items, int nb, int nnb, hipStream_t s);
 // FP32 spectrum as a polynomial in u = sin(theta): launch_acorr writes each
 // frame's lag sums h'_d into its group buffer as partial sums over blocks of
-// kAcorrRows rows (one workgroup per 256 lags and row block; reads U_s),
+// kAcorrRows rows (one two-wave workgroup per 256 lags and row block; reads U_s),
 // launch_hsum adds a group's partials in block order into the first block
 // (hsum_chunks(M) workgroups per group), launch_poly evaluates a group of up
 // to 16 frames over tiles of 64 nnb angles (nnb in {1, 2, 4}); the items of

@@ -12,9 +12,10 @@
 //
 // acorr: the lag sums h'_d of one frame in FP32 from U_s rounded to FP32, as
 //   partial sums over blocks of 256 rows (four adjacent lags per lane with a
-//   sliding register window, a one-wave workgroup per 256 lags and row
-//   block, so no lane runs longer than 4 x 256 K products; the columns staged
-//   through LDS; fixed order over k, then m).
+//   sliding register window, a two-wave workgroup per 256 lags and row
+//   block, each wave over 128 of its rows, so no lane runs longer than
+//   4 x 128 K products; the columns staged through LDS; fixed order over k,
+//   then m, then the two halves).
 // hsum:  adds each group's row-block partials in block order, once, into the
 //   first block, which the polynomial pass then reads.
 // poly:  frames with the same M and angle grid form groups of up to 16; the
@@ -35,22 +36,33 @@ using namespace steer;
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kAcL = 4;                        // adjacent lags per lane
-constexpr int kAcThreads = kAcorrLags / kAcL;  // one wave
+constexpr int kAcLanes = kAcorrLags / kAcL;    // lanes per lag chunk (one wave)
+constexpr int kAcWaves = 2;                    // waves per row block
+constexpr int kAcThreads = kAcLanes * kAcWaves;
+constexpr int kAcSub = kAcorrRows / kAcWaves;  // rows per wave
+static_assert(kAcLanes == 64, "one wave covers a lag chunk");
 
-// One workgroup (one wave): kAcorrLags consecutive lags d0.. of one frame,
-// kAcL adjacent lags per lane, over one block of kAcorrRows rows m; the
-// partial sums go to block `rb` of the group buffer.  A lane keeps the
-// kAcL values U[k][m + d] of its lags in registers and slides them by one
-// row per step (one new LDS value per kAcL products).  A lag's rows run to
-// M - 1 - d: the staged window is zero past M, so the extra products of a
-// lane's later lags add exact zeros.  Summation order within a block: k
-// outer, m ascending; the blocks are added in order by the polynomial pass.
+// One workgroup (two waves): kAcorrLags consecutive lags d0.. of one frame,
+// kAcL adjacent lags per lane, over one block of kAcorrRows rows m, each
+// wave taking half the block's rows; the block's partial sums (the first
+// half's plus the second's) go to block `rb` of the group buffer.  A lane
+// keeps the kAcL values U[k][m + d] of its lags in registers and slides them
+// by one row per step (one new LDS value per kAcL products).  A lag's rows
+// run to M - 1 - d: the staged window is zero past M, so the extra products
+// of a lane's later lags add exact zeros.  Summation order within a half
+// block: k outer, m ascending; the blocks are added in order by the
+// polynomial pass.
 template <bool kBatched>
 __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
                                                            const FrameDev *frames,
                                                            const Item *items) {
   __shared__ float2 wa[kAcorrRows];
-  __shared__ float2 wb[kAcorrRows + kAcorrLags + kAcL];
+  // the lag window, one float2 of padding after every 32: lane l reads
+  // element 4 l + c, and without the padding lanes l and l + 8 would hit the
+  // same LDS banks
+  constexpr int kWbN = kAcorrRows + kAcorrLags + kAcL;
+  __shared__ float2 wb[kWbN + kWbN / 32 + 1];
+  __shared__ float2 part[kAcL][kAcLanes];  // second wave's sums
   int chunk, rb;
   const FrameDev *fp;
   if constexpr (kBatched) {
@@ -68,9 +80,11 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
   FM_GLOBAL float2 *hg = (FM_GLOBAL float2 *)(fp->hgrp + (size_t)rb * M * kPolyRows);
   const int slot = fp->hslot;
   const int tid = threadIdx.x;
+  const int lane = tid & (kAcLanes - 1), wave = tid / kAcLanes;
   const int d0 = chunk * kAcorrLags;
-  const int dl = d0 + kAcL * tid;  // this lane's first lag
+  const int dl = d0 + kAcL * lane;          // this lane's first lag
   const int m0 = rb * kAcorrRows;
+  const int mw = m0 + wave * kAcSub;        // this wave's first row
   float re[kAcL], im[kAcL];
 #pragma unroll
   for (int j = 0; j < kAcL; ++j) re[j] = im[j] = 0.f;
@@ -78,7 +92,6 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
   // unconditional global loads (rows past M read row M - 1 and are staged as
   // zero), then staged in LDS as FP32 (the values of its FP32 copy)
   constexpr int kWa = kAcorrRows / kAcThreads;
-  constexpr int kWbN = kAcorrRows + kAcorrLags + kAcL;
   constexpr int kWb = (kWbN + kAcThreads - 1) / kAcThreads;
   const FM_GLOBAL double2 *Ug = (const FM_GLOBAL double2 *)Us;
   double2 pa[kWa], pb[kWb];
@@ -100,38 +113,53 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
     for (int i = 0; i < kWb; ++i) {
       const int e = tid + kAcThreads * i;
       const double2 v = m0 + d0 + e < M ? pb[i] : make_double2(0.0, 0.0);
-      if (e < kWbN) wb[e] = make_float2((float)v.x, (float)v.y);
+      if (e < kWbN) wb[e + (e >> 5)] = make_float2((float)v.x, (float)v.y);
     }
   };
   if (m0 + d0 < M) {  // uniform: some lag of this workgroup reaches the block
     fetch(0);
+    // rows of this wave's half used by the lane's first (longest) lag
+    const int cnt = min(kAcSub, M - dl - mw);
+    const int base = kAcL * lane + wave * kAcSub;
+    const float2 *wah = wa + wave * kAcSub;
     for (int k = 0; k < K; ++k) {
       __syncthreads();  // the previous column has been read
       stage();
       __syncthreads();
       fetch(min(k + 1, K - 1));
-      // rows of this block used by the lane's first (longest) lag
-      const int cnt = min(kAcorrRows, M - dl - m0);
       if (cnt > 0) {
-        const int base = kAcL * tid;
         float2 x[kAcL];
 #pragma unroll
-        for (int j = 0; j < kAcL; ++j) x[j] = wb[base + j];
+        for (int j = 0; j < kAcL; ++j) x[j] = wb[base + j + ((base + j) >> 5)];
 #pragma unroll 4
         for (int i = 0; i < cnt; ++i) {
-          const float2 y = wa[i];
+          const float2 y = wah[i];
 #pragma unroll
           for (int j = 0; j < kAcL; ++j) {
-            // conj(U[k][m + d]) * U[k][m], m = m0 + i, d = dl + j
+            // conj(U[k][m + d]) * U[k][m], m = mw + i, d = dl + j
             re[j] = fmaf(x[j].x, y.x, fmaf(x[j].y, y.y, re[j]));
             im[j] = fmaf(x[j].x, y.y, fmaf(-x[j].y, y.x, im[j]));
           }
 #pragma unroll
           for (int j = 0; j + 1 < kAcL; ++j) x[j] = x[j + 1];
-          x[kAcL - 1] = wb[base + i + kAcL];
+          const int e = base + i + kAcL;
+          x[kAcL - 1] = wb[e + (e >> 5)];
         }
       }
     }
+  }
+  // the block's sums: first half + second half
+  if (wave == 1) {
+#pragma unroll
+    for (int j = 0; j < kAcL; ++j) part[j][lane] = make_float2(re[j], im[j]);
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int j = 0; j < kAcL; ++j) {
+    const float2 o = part[j][lane];
+    re[j] += o.x;
+    im[j] += o.y;
   }
 #pragma unroll
   for (int j = 0; j < kAcL; ++j) {
