@@ -421,6 +421,9 @@ def main():
                 "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4),
                 "traffic": traffic,
+                # the measured HBM bytes per launch against the HBM peak
+                "traffic_frac_of_hbm_peak": (round(traffic / (cov_ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 4)
+                                             if traffic else None),
                 "launch_ms": round(cov_ms, 4),
                 "algorithmic_flops_per_launch": B * cov_flops(M, T),
                 # what the matrix cores execute: the FP32 kernel's three-product
@@ -477,6 +480,9 @@ def main():
             mixed[pname]["covariance_mfma_busy_frac"] = round(
                 B * cov_mfma_flops(M, T, pname) / (sm["covariance"] * 1e-3) / 1e12
                 / PEAK_F16_MFMA_TFLOPS, 4)
+            tr = pmc_traffic(B, pname)
+            mixed[pname]["covariance_traffic_frac_of_hbm_peak"] = (
+                round(tr / (sm["covariance"] * 1e-3) / (PEAK_HBM_GBS * 1e9), 4) if tr else None)
             dP = max(float(np.max(np.abs(10 * np.log10(
                 frames2[i].P.double().cpu().numpy() / P_main[i])))) for i in range(n_chk))
             mixed[pname]["max_abs_dP_dB_vs_main_step"] = float(f"{dP:.3g}")
