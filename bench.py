@@ -320,8 +320,8 @@ def main():
     args = ap.parse_args()
     legs = set() if args.no_extra else {x for x in args.legs.split(",") if x}
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
-              "multi-GPU form in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no "
+              "multi-GPU form (one process drives one GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch

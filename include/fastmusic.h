@@ -58,7 +58,7 @@ typedef enum {
   FM_E_ARG = 1,          /* invalid argument; nothing launched */
   FM_E_HIP = 2,          /* HIP runtime error (message in fm_last_error) */
   FM_E_WORKSPACE = 3,    /* arena too small for this call */
-  FM_E_UNSUPPORTED = 4   /* valid but not supported by this build */
+  FM_E_UNSUPPORTED = 4   /* valid but not supported by this library */
 } fm_status;
 
 /* Operand precision of the matrix-core products.  Accumulation is FP32 in
