@@ -41,6 +41,7 @@ constexpr int kAcWaves = 2;                    // waves per row block
 constexpr int kAcThreads = kAcLanes * kAcWaves;
 constexpr int kAcSub = kAcorrRows / kAcWaves;  // rows per wave
 static_assert(kAcLanes == 64, "one wave covers a lag chunk");
+constexpr int kPadShift = kAcL == 4 ? 3 : 4;   // lag-window padding period 8 (16 for 8 lags)
 
 // One workgroup (two waves): kAcorrLags consecutive lags d0.. of one frame,
 // kAcL adjacent lags per lane, over one block of kAcorrRows rows m, each
@@ -57,11 +58,11 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
                                                            const FrameDev *frames,
                                                            const Item *items) {
   __shared__ float2 wa[kAcorrRows];
-  // the lag window, one float2 of padding after every 32: lane l reads
-  // element 4 l + c, and without the padding lanes l and l + 8 would hit the
-  // same LDS banks
+  // the lag window, one float2 of padding after every 2^kPadShift: lane l
+  // reads element kAcL l + c, and without the padding lanes 64 / kAcL apart
+  // would hit the same LDS banks (with it, at most two lanes share a bank)
   constexpr int kWbN = kAcorrRows + kAcorrLags + kAcL;
-  __shared__ float2 wb[kWbN + kWbN / 32 + 1];
+  __shared__ float2 wb[kWbN + (kWbN >> kPadShift) + 1];
   __shared__ float2 part[kAcL][kAcLanes];  // second wave's sums
   int chunk, rb;
   const FrameDev *fp;
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
     for (int i = 0; i < kWb; ++i) {
       const int e = tid + kAcThreads * i;
       const double2 v = m0 + d0 + e < M ? pb[i] : make_double2(0.0, 0.0);
-      if (e < kWbN) wb[e + (e >> 5)] = make_float2((float)v.x, (float)v.y);
+      if (e < kWbN) wb[e + (e >> kPadShift)] = make_float2((float)v.x, (float)v.y);
     }
   };
   if (m0 + d0 < M) {  // uniform: some lag of this workgroup reaches the block
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
       if (cnt > 0) {
         float2 x[kAcL];
 #pragma unroll
-        for (int j = 0; j < kAcL; ++j) x[j] = wb[base + j + ((base + j) >> 5)];
+        for (int j = 0; j < kAcL; ++j) x[j] = wb[base + j + ((base + j) >> kPadShift)];
 #pragma unroll 4
         for (int i = 0; i < cnt; ++i) {
           const float2 y = wah[i];
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
 #pragma unroll
           for (int j = 0; j + 1 < kAcL; ++j) x[j] = x[j + 1];
           const int e = base + i + kAcL;
-          x[kAcL - 1] = wb[e + (e >> 5)];
+          x[kAcL - 1] = wb[e + (e >> kPadShift)];
         }
       }
     }
