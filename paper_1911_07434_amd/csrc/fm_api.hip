@@ -179,6 +179,14 @@ fm_status check_cov(fm_ctx *c, const void *X, int M, int T, int64_t ldx, const v
   return FM_OK;
 }
 
+// the 16-bit covariance kernels address rows through 32-bit lane offsets
+fm_status check_cov16_ldx(fm_ctx *c, int64_t ldx, fm_prec prec) {
+  if (prec != FM_FP32 && ldx > fm::kCov16MaxLdx)
+    return fail(c, FM_E_UNSUPPORTED, "covariance: ldx (%lld) > %lld for 16-bit operands",
+                (long long)ldx, fm::kCov16MaxLdx);
+  return FM_OK;
+}
+
 fm_status check_sub(fm_ctx *c, const void *R, int M, int64_t ldr, int method, int n, int q,
                     int K, double rcond, const void *rnd, const void *Us, const void *sigma,
                     const void *status) {
@@ -366,6 +374,7 @@ FM_API fm_status fm_covariance(fm_ctx *ctx, void *stream, const void *X, int M, 
   fm_status st = check_cov(ctx, X, M, T, ldx, R, ldr);
   if (st != FM_OK) return st;
   if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "covariance: bad precision %d", (int)prec);
+  if ((st = check_cov16_ldx(ctx, ldx, prec)) != FM_OK) return st;
   if ((st = set_dev(ctx)) != FM_OK) return st;
   FrameDev f = blank_frame();
   f.X = static_cast<const float2 *>(X);
@@ -686,6 +695,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     const bool from_x = a.method == FM_METHOD_PROJECT_X || a.method == FM_METHOD_SAMPLE_X;
     fm_status st = check_cov(ctx, a.X, a.M, a.T, a.ldx, from_x ? a.X : a.R,
                              from_x ? a.M : a.ldr);
+    if (st == FM_OK && !from_x) st = check_cov16_ldx(ctx, a.ldx, prec);
     if (st == FM_OK)
       st = check_sub(ctx, from_x ? a.X : a.R, a.M, from_x ? a.M : a.ldr, a.method, a.n, a.q,
                      a.K, a.rcond,
@@ -853,16 +863,16 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
       if (sched == 0) {
         // the whole frame onto the least-loaded XCD
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        fm::cov_each_unit(frames[i].M, prec, [&](int a, int b) {
+        fm::cov_each_unit(frames[i].M, prec, [&](int a, int b, int kind) {
           load[x] += frames[i].T;
-          q[x].push_back({i, a, b, 0});
+          q[x].push_back({i, a, b, kind});
         });
       } else {
         // each unit onto the least-loaded XCD
-        fm::cov_each_unit(frames[i].M, prec, [&](int a, int b) {
+        fm::cov_each_unit(frames[i].M, prec, [&](int a, int b, int kind) {
           const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
           load[x] += frames[i].T;
-          q[x].push_back({i, a, b, 0});
+          q[x].push_back({i, a, b, kind});
         });
       }
     }

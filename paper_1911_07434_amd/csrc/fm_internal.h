@@ -196,10 +196,13 @@ hipError_t launch_refine(const FrameDev &single, const FrameDev *frames, const I
 hipError_t launch_peaks(const FrameDev &single, const FrameDev *frames, const Item *items,
                         int n_items, hipStream_t s);
 
-// Covariance work units of one frame.  16-bit: one workgroup per 128x128
-// tile (ti, tj <= ti) of the lower triangle.  FP32: one wave per 64x32 block
-// (bi, bj) with bj <= 2 bi + 1 (the blocks of 64-row block bi that reach the
+// Covariance work units of one frame.  16-bit: one workgroup per unit of
+// 128x128 tiles: off-diagonal tiles (a, b < a), diagonal tiles in pairs
+// (a, b > a) and, for an odd number of row tiles, the middle diagonal tile
+// alone (kinds below, in Item::c).  FP32: one wave per 64x32 block (bi, bj)
+// with bj <= 2 bi + 1 (the blocks of 64-row block bi that reach the
 // diagonal), bj < ceil(M / 32).
+enum Cov16Kind { kCov16Off = 0, kCov16Diag2 = 1, kCov16Diag1 = 2 };
 inline int cov_edge(fm_prec prec) { return prec == FM_FP32 ? kCovBlock : kCovTile; }
 
 // units a single-frame launch covers (FP32: whole block rows; units whose
@@ -207,21 +210,72 @@ inline int cov_edge(fm_prec prec) { return prec == FM_FP32 ? kCovBlock : kCovTil
 inline int cov_units(int M, fm_prec prec) {
   const int e = cov_edge(prec);
   const int nt = (M + e - 1) / e;
-  return prec == FM_FP32 ? nt * (nt + 1) : nt * (nt + 1) / 2;
+  return prec == FM_FP32 ? nt * (nt + 1) : nt * (nt - 1) / 2 + (nt + 1) / 2;
 }
 
-// every non-empty unit (a, b) of a frame, in row order
+namespace detail {
+// 16-bit units of the row tiles [lo, lo + n) of a frame in an order where
+// each run of 32 consecutive units touches few row tiles: a triangle of at
+// most 8 row tiles is 32 units or fewer (its off-diagonal tiles, then its
+// diagonal pairs); a larger one is split into two triangles and the square
+// between them, cut into rectangles of at most 32 tiles.  The sub-block
+// products do not depend on which tile a diagonal tile is paired with, so
+// this order and the single-frame launch's give the same bits.
+template <class F>
+inline void cov16_square(int r0, int nr, int c0, int nc, F &fn) {
+  if (nr * nc <= 32) {
+    for (int a = r0; a < r0 + nr; ++a)
+      for (int b = c0; b < c0 + nc; ++b) fn(a, b, (int)kCov16Off);
+  } else if (nr >= nc) {
+    cov16_square(r0, nr / 2, c0, nc, fn);
+    cov16_square(r0 + nr / 2, nr - nr / 2, c0, nc, fn);
+  } else {
+    cov16_square(r0, nr, c0, nc / 2, fn);
+    cov16_square(r0, nr, c0 + nc / 2, nc - nc / 2, fn);
+  }
+}
+// `pend`: a diagonal tile left over by an odd triangle, waiting for a partner
+template <class F>
+inline void cov16_triangle(int lo, int n, int &pend, F &fn) {
+  if (n <= 8) {
+    for (int a = lo + 1; a < lo + n; ++a)
+      for (int b = lo; b < a; ++b) fn(a, b, (int)kCov16Off);
+    for (int d = 0; d < n / 2; ++d) fn(lo + d, lo + n - 1 - d, (int)kCov16Diag2);
+    if (n % 2) {
+      if (pend >= 0) {
+        fn(pend, lo + n / 2, (int)kCov16Diag2);
+        pend = -1;
+      } else {
+        pend = lo + n / 2;
+      }
+    }
+    return;
+  }
+  const int h = n / 2;
+  cov16_triangle(lo, h, pend, fn);
+  cov16_square(lo + h, n - h, lo, h, fn);
+  cov16_triangle(lo + h, n - h, pend, fn);
+}
+}  // namespace detail
+
+// every non-empty unit (a, b, kind) of a frame: FP32 in row order (kind 0),
+// 16-bit in the locality order above
 template <class F>
 inline void cov_each_unit(int M, fm_prec prec, F &&fn) {
   const int e = cov_edge(prec);
   const int nt = (M + e - 1) / e;
-  for (int a = 0; a < nt; ++a) {
-    if (prec == FM_FP32) {
-      for (int b = 0; b <= 2 * a + 1 && b * kCovCols < M; ++b) fn(a, b);
-    } else {
-      for (int b = 0; b <= a; ++b) fn(a, b);
-    }
+  if (prec == FM_FP32) {
+    for (int a = 0; a < nt; ++a)
+      for (int b = 0; b <= 2 * a + 1 && b * kCovCols < M; ++b) fn(a, b, 0);
+  } else {
+    int pend = -1;
+    detail::cov16_triangle(0, nt, pend, fn);
+    if (pend >= 0) fn(pend, pend, (int)kCov16Diag1);
   }
 }
+
+// largest leading dimension of X the 16-bit covariance takes: it addresses
+// a 128-row tile of X through 32-bit byte offsets (128 ldx 8 <= 2^32)
+constexpr long long kCov16MaxLdx = 1LL << 22;
 
 }  // namespace fm
