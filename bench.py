@@ -328,6 +328,7 @@ def main():
 
     import fmsynth
     import paper_1911_07434_amd as fm
+    from paper_1911_07434_amd.comparator import plain_music_batch
     from paper_1911_07434_amd.frames import DeviceFrame, FrameSpec
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -628,15 +629,7 @@ def main():
         nb = min(B, 32)
         with torch.cuda.stream(stream):
             def plain_batch():
-                Rs = torch.empty((nb, M, M), dtype=torch.complex64, device="cuda")
-                for i in range(nb):
-                    ctx.fm_covariance(X[i], Rs[i], stream=stream)
-                w, V = torch.linalg.eigh(Rs)             # ascending eigenvalues
-                Us = V[:, :, M - K:].flip(-1).transpose(1, 2).to(torch.complex128).contiguous()
-                for i in range(nb):
-                    d = frames2[i]
-                    ctx.fm_pseudospectrum(Us[i], th0, dth, L_GRID, d.P, stream=stream)
-                    ctx.fm_peaks(d.P, K, d.peak_idx, d.peak_val, d.n_found, stream=stream)
+                plain_music_batch(ctx, frames2[:nb], K, th0, dth, L_GRID, stream=stream)
             plain_batch()
             torch.cuda.synchronize()
             t0 = time.perf_counter()

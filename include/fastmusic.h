@@ -108,14 +108,31 @@ typedef enum {
                               null); see fm_subspace_sample_x */
 } fm_method;
 
-/* per-frame device status bits */
-#define FM_ST_NONFINITE      1u  /* NaN/Inf met in an input or intermediate */
+/* per-frame device status bits, written by the subspace stage (the peak and
+ * model-order bits OR-ed in by the stages that find them).  Outputs are
+ * meaningful only if status & (FM_ST_NONFINITE | FM_ST_BAD_INDEX) == 0. */
+#define FM_ST_NONFINITE      1u  /* NaN/Inf in the final sketch Gram matrix or
+                                    its eigenvalues: a NaN or Inf in X or R
+                                    reaches every entry of it */
+#define FM_ST_ORTH_FALLBACK  2u  /* a Cholesky QR of a sketch (orth() of
+                                    Alg. 2) met a pivot below 1e-10 of the
+                                    largest diagonal entry; that step used the
+                                    Gram eigen-route instead (same span) */
 #define FM_ST_EIG_MAXIT      4u  /* a Jacobi eigen-solve hit its sweep limit */
 #define FM_ST_RANK_DEFICIENT 8u  /* fewer than K non-zero directions survived */
 #define FM_ST_FEW_PEAKS     16u  /* fewer than K local maxima */
 #define FM_ST_BAD_INDEX     32u  /* sampled index outside [0, M) or repeated */
 #define FM_ST_ORDER_AT_LIMIT 64u  /* model-order estimate equals the sketch width
                                     n: the sketch was too narrow to bound it */
+#define FM_ST_CORE_TRUNCATED 128u /* the pseudo-inverse of the core (eq. (8))
+                                     kept fewer than n eigen-directions (those
+                                     <= rcond * the largest were dropped); the
+                                     kept rank is the number of non-zero
+                                     entries of the model-order eigenvalue
+                                     array (plans) or of sigma when K = n */
+/* the bits that describe how a result was reached (expected with noiseless
+ * or very high-SNR frames, or T < n), not a failure */
+#define FM_ST_NOTES (FM_ST_ORTH_FALLBACK | FM_ST_CORE_TRUNCATED)
 
 /* Default relative threshold of the eigen-based pseudo-inverse, eq. (8):
  * eigenvalues lambda <= rcond * lambda_max of the p x p (or l x l) core are

@@ -21,7 +21,13 @@ FM_FP32, FM_BF16, FM_FP16, FM_FP16X3, FM_BF16X3 = 0, 1, 2, 3, 4
 FM_METHOD_PROJECT, FM_METHOD_SAMPLE, FM_METHOD_PROJECT_X, FM_METHOD_SAMPLE_X = 0, 1, 2, 3
 FM_ST_NONFINITE, FM_ST_EIG_MAXIT, FM_ST_RANK_DEFICIENT, FM_ST_FEW_PEAKS, FM_ST_BAD_INDEX = (
     1, 4, 8, 16, 32)
-FM_ST_ORDER_AT_LIMIT = 64
+FM_ST_ORTH_FALLBACK, FM_ST_ORDER_AT_LIMIT, FM_ST_CORE_TRUNCATED = 2, 64, 128
+FM_ST_NOTES = FM_ST_ORTH_FALLBACK | FM_ST_CORE_TRUNCATED
+
+
+def status_errors(status) -> int:
+    """The status bits of a frame that are not FM_ST_NOTES (0: a clean result)."""
+    return int(status) & ~FM_ST_NOTES
 FM_ORDER_AIC, FM_ORDER_MDL = 0, 1
 FM_RCOND_DEFAULT = 1e-6
 FM_KNOB_COV_SCHEDULE, FM_KNOB_SPEC_ANGLES, FM_KNOB_SPEC16_ANGLES = 0, 1, 2

@@ -881,6 +881,7 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
         return;
       }
       // the failed attempt overwrote A: reload the Gram for the eigen route
+      if (threadIdx.x == 0) *wstat_of(f) |= FM_ST_ORTH_FALLBACK;
       load_herm(A, V, np, n, f.part, f.nchunk, 0, nullptr);
     }
     // V_new = Y E diag(lambda^-1/2): orthonormal basis of the sketch
@@ -919,6 +920,9 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
         b = cadd(b, pc[(size_t)j * n + i]);
       }
       v = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
+      // a NaN or Inf anywhere in X or R reaches every entry of the sketch's
+      // (or the sampled columns') Gram matrix
+      if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(&S.st, (unsigned)FM_ST_NONFINITE);
     }
     Gc[e] = v;
   }
@@ -933,6 +937,9 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
     for (int k = 0; k < n; ++k)
       if (S.w[k] > thr && S.w[k] > 0.0) ++r;
     S.rank = r;
+    // the pseudo-inverse of eq. (8) dropped directions of the core
+    if (r < n) S.st |= FM_ST_CORE_TRUNCATED;
+    if (!isfinite(S.w[0])) S.st |= FM_ST_NONFINITE;
   }
   __syncthreads();
   const int r1 = S.rank;

@@ -24,10 +24,15 @@ M, T, K, L_SK, Q, L = 4096, 8192, 16, 24, 2, 36001
 # FP32 path 1e-3 dB, mixed paths 1e-2 dB.  BF16 operands (8-bit mantissa)
 # meet the mixed budget up to 10 dB; at 30 dB the peak-region denominators
 # are so small that BF16 rounding of the snapshots moves them by ~0.015 dB
-# (measured on an MI355X), so BF16 is reported but not asserted there.
-# The split precisions (hi + lo halves, three 16-bit products) carry
-# FP32-level error and are held to the FP32 bar at every SNR.
+# (measured on an MI355X): that one cell is a strict expected failure below
+# (its status and AoA checks still run in the per-SNR test).  The split
+# precisions (hi + lo halves, three 16-bit products) carry FP32-level error
+# and are held to the FP32 bar at every SNR.
 BARS_DB = {"fp32": 1e-3, "fp16": 1e-2, "bf16": 1e-2, "fp16x3": 1e-3, "bf16x3": 1e-3}
+PRECS = (("fp32", fm.FM_FP32), ("fp16", fm.FM_FP16), ("bf16", fm.FM_BF16),
+         ("fp16x3", fm.FM_FP16X3), ("bf16x3", fm.FM_BF16X3))
+# the dB bar of this cell is asserted in its own strict-xfail test
+KNOWN_OVER_BAR = {("bf16", 30.0)}
 
 
 @pytest.fixture(scope="module")
@@ -39,8 +44,13 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("snr", [-10.0, 0.0, 10.0, 30.0])
-def test_config4_mixed_precision_per_snr(ctx, snr):
+_cache = {}
+
+
+def _run_snr(ctx, snr):
+    """GPU results at every precision and the oracle's, for one SNR (cached)."""
+    if snr in _cache:
+        return _cache[snr]
     seed = 4000 + int(snr)
     fr = fmsynth.make_frame(M, T, K, snr, seed, angle_range=(-75.0, 75.0), pairs=0.5,
                             pair_center_sep=2.0)
@@ -51,15 +61,15 @@ def test_config4_mixed_precision_per_snr(ctx, snr):
     X = torch.from_numpy(fr.X).cuda()
     Omd = torch.from_numpy(Om).cuda()
     got = {}
-    for name, prec in (("fp32", fm.FM_FP32), ("fp16", fm.FM_FP16), ("bf16", fm.FM_BF16),
-                       ("fp16x3", fm.FM_FP16X3), ("bf16x3", fm.FM_BF16X3)):
+    for name, prec in PRECS:
         d = DeviceFrame(spec, X=X, rnd=Omd)
         plan = fm.Plan(ctx, [d.descriptor()], prec=prec)
         plan.run()
         torch.cuda.synchronize()
         plan.close()
-        got[name] = d.results()
-        del d
+        r = d.results()
+        got[name] = {k: r[k] for k in ("P", "status", "peak_idx")}
+        del d, r
     thr = oracle.default_threads()
     R = oracle.covariance(fr.X, threads=thr)
     Us, sig, _ = oracle.subspace_project(R, Om, Q, K)
@@ -72,10 +82,23 @@ def test_config4_mixed_precision_per_snr(ctx, snr):
         near = all(np.min(np.abs(g["peak_idx"] - p)) <= 1 for p in pi_o)
         print(f"config4 SNR {snr:+.0f} dB {name}: max |dP| = {errs[name]:.3g} dB, "
               f"peaks within one step: {near}, status {g['status']}", flush=True)
+    _cache[snr] = (got, errs, pi_o)
+    return _cache[snr]
+
+
+@pytest.mark.parametrize("snr", [-10.0, 0.0, 10.0, 30.0])
+def test_config4_mixed_precision_per_snr(ctx, snr):
+    got, errs, pi_o = _run_snr(ctx, snr)
     for name, bar in BARS_DB.items():
-        if name == "bf16" and snr > 10.0:
-            continue
-        assert got[name]["status"] == 0
-        assert errs[name] <= bar, (name, errs[name])
+        assert fm.status_errors(got[name]["status"]) == 0, name
+        if (name, snr) not in KNOWN_OVER_BAR:
+            assert errs[name] <= bar, (name, errs[name])
         for p in pi_o:
-            assert np.min(np.abs(got[name]["peak_idx"] - p)) <= 1
+            assert np.min(np.abs(got[name]["peak_idx"] - p)) <= 1, name
+
+
+@pytest.mark.xfail(strict=True, reason="BF16 rounding of the snapshots: about 1.5e-2 dB at "
+                                       "30 dB SNR, over the 1e-2 dB mixed-path bar")
+def test_config4_bf16_30db_mixed_bar(ctx):
+    _got, errs, _pi = _run_snr(ctx, 30.0)
+    assert errs["bf16"] <= BARS_DB["bf16"]

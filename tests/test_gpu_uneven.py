@@ -133,8 +133,14 @@ def test_autotune_installs_valid_choices_and_keeps_bits(ctx, tmp_path):
 
 @pytest.fixture(scope="module")
 def uneven_workload():
-    """Four frames of the uneven workload and their oracle results."""
-    shapes = fmsynth.uneven_batch(4, seed=73)
+    """Eight frames of the uneven workload, two of each M in {256, 512, 1024,
+    2048} (the first two of each M drawn from one seeded batch), and their
+    oracle results."""
+    shapes = []
+    for s in fmsynth.uneven_batch(64, seed=73):
+        if sum(1 for t in shapes if t["M"] == s["M"]) < 2:
+            shapes.append(s)
+    assert sorted({s["M"] for s in shapes}) == [256, 512, 1024, 2048] and len(shapes) == 8
     th0, dth, L = fmsynth.grid(18001)
     frames, refs = [], []
     for s in shapes:
@@ -149,17 +155,44 @@ def uneven_workload():
     return frames, refs
 
 
-# split precisions carry FP32-level error: the FP32 bar
-@pytest.mark.parametrize("prec,bar", [(fm.FM_FP32, 1e-3), (fm.FM_FP16, 1e-2),
+# split precisions carry FP32-level error: the FP32 bar.  BF16 operands keep
+# 8 significant bits: on two small frames (2: M=256, T=237, K=13, 7.8 dB and
+# 4: M=256, T=287, K=7, 17.2 dB) their rounding moves the spectrum by
+# ~0.019 and ~0.011 dB, over the 1e-2 dB mixed-path bar; those cells' dB
+# checks are strict expected failures below (their status and AoA checks run
+# here).
+KNOWN_OVER_BAR = {(fm.FM_BF16, 2), (fm.FM_BF16, 4)}
+_got = {}
+
+
+def _uneven_run(ctx, frames, prec):
+    if prec not in _got:
+        _got[prec] = [{k: r[k] for k in ("P", "status", "n_found", "peak_idx")}
+                      for r in _run(ctx, frames, prec, use_graph=True)]
+    return _got[prec]
+
+
+@pytest.mark.parametrize("prec,bar", [(fm.FM_FP32, 1e-3), (fm.FM_FP16, 1e-2), (fm.FM_BF16, 1e-2),
                                       (fm.FM_FP16X3, 1e-3), (fm.FM_BF16X3, 1e-3)])
 def test_uneven_workload_frames_match_oracle(ctx, uneven_workload, prec, bar):
     frames, refs = uneven_workload
-    got = _run(ctx, frames, prec, use_graph=True)
-    for (spec, _X, _Om), g, ref in zip(frames, got, refs):
+    got = _uneven_run(ctx, frames, prec)
+    for i, ((spec, _X, _Om), g, ref) in enumerate(zip(frames, got, refs)):
         err = float(np.max(np.abs(10 * np.log10(g["P"].astype(np.float64) / ref["P"]))))
         say(f"  M={spec.M} T={spec.T} K={spec.K}: max |dP| = {err:.3g} dB")
-        assert g["status"] == 0
-        assert err <= bar
+        assert fm.status_errors(g["status"]) == 0
+        if (prec, i) not in KNOWN_OVER_BAR:
+            assert err <= bar
         assert g["n_found"] == len(ref["peak_idx"])
         for pk in ref["peak_idx"]:
             assert np.min(np.abs(g["peak_idx"] - pk)) <= 1
+
+
+@pytest.mark.xfail(strict=True, reason="BF16 rounding of the snapshots on small M=256 frames: "
+                                       "about 1.1e-2 and 1.9e-2 dB, over the 1e-2 dB bar")
+@pytest.mark.parametrize("i", [2, 4])
+def test_uneven_bf16_small_frame_mixed_bar(ctx, uneven_workload, i):
+    frames, refs = uneven_workload
+    got = _uneven_run(ctx, frames, fm.FM_BF16)
+    err = float(np.max(np.abs(10 * np.log10(got[i]["P"].astype(np.float64) / refs[i]["P"]))))
+    assert err <= 1e-2
