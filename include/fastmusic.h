@@ -213,6 +213,23 @@ fm_status fm_subspace_project(fm_ctx *ctx, void *stream, const void *R, int M, i
                               const float *Omega, int l, int q, int K, double rcond,
                               fm_prec prec, void *Us, double *sigma, uint32_t *status);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as fm_subspace_project -- the same kernels, bit-identical
+ * results -- with its workspace in a fixed device array of
+ * FM_NOALLOC_SCRATCH_BYTES that the library holds on each GPU until the
+ * process ends (its address is taken once, by fm_create).  The call
+ * allocates nothing and does not use the context's arena.  Requires
+ * fm_workspace_bytes(M, l, K, 0) <= FM_NOALLOC_SCRATCH_BYTES (FM_E_WORKSPACE
+ * otherwise; e.g. M = 4096 with l = K = 64 fits).  Every call on one GPU
+ * shares the array: calls that overlap on a GPU (other streams, other
+ * contexts, other threads) race and must be serialised by the caller. */
+#define FM_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+fm_status fm_subspace_project_noalloc(fm_ctx *ctx, void *stream, const void *R, int M,
+                                      int64_t ldr, const float *Omega, int l, int q, int K,
+                                      double rcond, fm_prec prec, void *Us, double *sigma,
+                                      uint32_t *status);
+
 /* Method 1 straight from the snapshots: the same algorithm as
  * fm_subspace_sample on R = X X^H / T, with the sampled columns formed as
  * C = R(:, I) = X X(I, :)^H / T and the core R(I, I) taken from C(I, :) --

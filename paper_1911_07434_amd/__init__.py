@@ -31,6 +31,7 @@ def status_errors(status) -> int:
 FM_ORDER_AIC, FM_ORDER_MDL = 0, 1
 FM_RCOND_DEFAULT = 1e-6
 FM_KNOB_COV_SCHEDULE, FM_KNOB_SPEC_ANGLES, FM_KNOB_SPEC16_ANGLES = 0, 1, 2
+FM_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 # every symbol of include/fastmusic.h
 EXPORTS = (
@@ -40,6 +41,7 @@ EXPORTS = (
     "fm_plan_covariance", "fm_plan_subspace", "fm_plan_pseudospectrum", "fm_plan_peaks",
     "fm_plan_run", "fm_plan_bytes", "fm_plan_create_in", "fm_set_knob", "fm_get_knob",
     "fm_subspace_project_x", "fm_subspace_sample_x", "fm_order", "fm_esprit",
+    "fm_subspace_project_noalloc",
 )
 
 
@@ -107,6 +109,7 @@ def load_library(path: str = LIB_PATH):
         "fm_get_knob": ([P, I, I], I),
         "fm_order": ([P, P, P, I, I64, I, P, I, D, I, P, P, P], I),
         "fm_esprit": ([P, P, P, I, I, P, P], I),
+        "fm_subspace_project_noalloc": ([P, P, P, I, I64, P, I, I, I, D, I, P, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -182,6 +185,15 @@ class Context:
                                                 R.stride(0), _ptr(Omega), Omega.shape[1], q, K,
                                                 rcond, prec, _ptr(Us), _ptr(sigma),
                                                 _ptr(status)))
+
+    def fm_subspace_project_noalloc(self, R, Omega, q, K, Us, sigma, status,
+                                    rcond=FM_RCOND_DEFAULT, prec=FM_FP32, stream=None):
+        """fm_subspace_project with the library's fixed device scratch array as
+        its workspace: allocates nothing (FM_NOALLOC_SCRATCH_BYTES at most)."""
+        M = R.shape[0]
+        self.check(self.lib.fm_subspace_project_noalloc(
+            self.h, _stream(stream), _ptr(R), M, R.stride(0), _ptr(Omega), Omega.shape[1], q, K,
+            rcond, prec, _ptr(Us), _ptr(sigma), _ptr(status)))
 
     def fm_subspace_project_x(self, X, Omega, q, K, Us, sigma, status, rcond=FM_RCOND_DEFAULT,
                               prec=FM_FP32, stream=None):

@@ -26,9 +26,21 @@ struct fm_ctx {
   int device = 0;
   char *arena = nullptr;
   size_t arena_bytes = 0;
+  // device address of `scratch` (below) on this context's device, from
+  // hipGetSymbolAddress at fm_create: the array's host-side name is not a
+  // device address
+  char *scratch = nullptr;
   std::string err;
   int knob[kKnobs][kBuckets];
 };
+
+// Workspace of fm_subspace_project_noalloc: a fixed device array, one copy
+// per GPU the library runs on, held until the process ends.  Every call on a
+// GPU shares it (concurrent calls on one GPU race); each call's kernels
+// initialise what they read, so nothing needs clearing between calls.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static_assert(kScratchBytes == FM_NOALLOC_SCRATCH_BYTES, "header limit");
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 namespace {
 
@@ -334,6 +346,13 @@ FM_API fm_status fm_create(int device, size_t workspace_bytes, fm_ctx **out) {
     delete c;
     return FM_E_HIP;
   }
+  // with the context's device current: this device's copy of `scratch`
+  if (hipGetSymbolAddress((void **)&c->scratch, HIP_SYMBOL(scratch)) != hipSuccess ||
+      !c->scratch) {
+    hipFree(c->arena);
+    delete c;
+    return FM_E_HIP;
+  }
   *out = c;
   return FM_OK;
 }
@@ -387,18 +406,23 @@ FM_API fm_status fm_covariance(fm_ctx *ctx, void *stream, const void *X, int M, 
   return FM_OK;
 }
 
+// `noalloc`: the workspace is this device's `scratch` array instead of the
+// context's arena
 static fm_status subspace_single(fm_ctx *ctx, void *stream, const void *R, int M, int64_t ldr,
                                  int method, const void *rnd, int n, int q, int K, double rcond,
-                                 fm_prec prec, void *Us, double *sigma, uint32_t *status) {
+                                 fm_prec prec, void *Us, double *sigma, uint32_t *status,
+                                 bool noalloc = false) {
   if (!ctx) return FM_E_ARG;
   fm_status st = check_sub(ctx, R, M, ldr, method, n, q, K, rcond, rnd, Us, sigma, status);
   if (st != FM_OK) return st;
   if (!prec_ok(prec)) return fail(ctx, FM_E_ARG, "subspace: bad precision %d", (int)prec);
 
   const WsLayout w = ws_layout(M, n, K, 0);
-  if (w.total > ctx->arena_bytes)
-    return fail(ctx, FM_E_WORKSPACE, "subspace: needs %zu arena bytes, have %zu", w.total,
-                ctx->arena_bytes);
+  char *const ws = noalloc ? ctx->scratch : ctx->arena;
+  const size_t ws_bytes = noalloc ? kScratchBytes : ctx->arena_bytes;
+  if (w.total > ws_bytes)
+    return fail(ctx, FM_E_WORKSPACE, "subspace: needs %zu %s bytes, have %zu", w.total,
+                noalloc ? "scratch" : "arena", ws_bytes);
   if ((st = set_dev(ctx)) != FM_OK) return st;
   FrameDev f = blank_frame();
   f.R = static_cast<float2 *>(const_cast<void *>(R));
@@ -414,7 +438,7 @@ static fm_status subspace_single(fm_ctx *ctx, void *stream, const void *R, int M
   f.Us = static_cast<double2 *>(Us);
   f.sigma = sigma;
   f.status = status;
-  bind_ws(f, ctx->arena, w);
+  bind_ws(f, ws, w);
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = method == FM_METHOD_PROJECT ? run_project_single(f, s, prec)
                                              : run_sample_single(f, s);
@@ -511,6 +535,14 @@ FM_API fm_status fm_subspace_project(fm_ctx *ctx, void *stream, const void *R, i
                                      uint32_t *status) {
   return subspace_single(ctx, stream, R, M, ldr, FM_METHOD_PROJECT, Omega, l, q, K, rcond, prec,
                          Us, sigma, status);
+}
+
+FM_API fm_status fm_subspace_project_noalloc(fm_ctx *ctx, void *stream, const void *R, int M,
+                                             int64_t ldr, const float *Omega, int l, int q, int K,
+                                             double rcond, fm_prec prec, void *Us,
+                                             double *sigma, uint32_t *status) {
+  return subspace_single(ctx, stream, R, M, ldr, FM_METHOD_PROJECT, Omega, l, q, K, rcond, prec,
+                         Us, sigma, status, true);
 }
 
 FM_API fm_status fm_order(fm_ctx *ctx, void *stream, const void *R, int M, int64_t ldr, int T,
