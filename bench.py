@@ -88,10 +88,14 @@ def pmc_traffic(n_frames, prec="fp32"):
 def serve_legs(ctx, fm, torch, seconds, seed):
     """Serving workload: Poisson arrivals at 2000 frames/s, M uniform over
     {128..4096} (powers of two), T ~ U[64, 4096], K ~ U[1, 32], SNR ~
-    U[-10, 30] dB, l = min(K+8, 40), q = 2, 18001-angle grid; continuous
-    batching on two streams with HBM-budget admission.  Standard MUSIC
-    (rocSOLVER eigen-decomposition per frame) is run on the head of the same
-    arrival trace."""
+    U[-10, 30] dB per frame, l = min(K+8, 40), q = 2, 18001-angle grid;
+    every frame's own snapshots generated into the pool when its batch is
+    launched; continuous batching on two streams with HBM-budget admission
+    (the budget counts snapshots, covariance, outputs and plans).  The mixed
+    path runs again with a budget of twice its mean in-flight bytes, which
+    binds: admission waits are reported.  Standard MUSIC (rocSOLVER
+    eigen-decomposition per frame) is run on the head of the same arrival
+    trace."""
     from paper_1911_07434_amd.serve import GpuExecutor, Server, WallClock, poisson_arrivals
     free, _total = torch.cuda.mem_get_info()
     budget = int(min(200 << 30, free - (24 << 30)))
@@ -108,6 +112,18 @@ def serve_legs(ctx, fm, torch, seconds, seed):
         log(f"serving {pname}: {res[pname]}")
         del ex
         torch.cuda.empty_cache()
+    # the mixed path again, with a budget that binds
+    bound = int(2 * res["fp16"]["mean_inflight_bytes"]) // 256 * 256
+    reqs = poisson_arrivals(2000.0, seconds, seed=seed + 1)
+    ex = GpuExecutor(ctx, pool_bytes=bound, n_streams=2, prec=fm.FM_FP16)
+    clock = WallClock()
+    ex.start(clock)
+    st = Server(ex, budget_bytes=bound, n_streams=2, max_batch=64, clock=clock).run(reqs)
+    torch.cuda.synchronize()
+    res["fp16_budget_bound"] = {"hbm_budget_bytes": bound, **st.summary()}
+    log(f"serving fp16, budget {bound / 2**30:.2f} GiB: {res['fp16_budget_bound']}")
+    del ex
+    torch.cuda.empty_cache()
     # standard MUSIC under the same arrivals (head of the trace)
     reqs = poisson_arrivals(2000.0, seconds, seed=seed + 1, max_frames=120)
     ex = PlainMusicExecutor(ctx, pool_bytes=min(budget, 64 << 30), n_streams=2)
@@ -268,7 +284,9 @@ def _plain_music_executor():
                     o = r.mem[0]
                     R = self.pool[o + lay["R"]:o + lay["R"] + r.M * r.M * 8].view(
                         torch.complex64).view(r.M, r.M)
-                    self.ctx.fm_covariance(self.X[r.M][:, :r.T], R, stream=s)
+                    X = self.X_view(r)
+                    self.make_X(r, X)
+                    self.ctx.fm_covariance(X, R, stream=s)
                     _w, V = torch.linalg.eigh(R)
                     Us = V[:, r.M - r.K:].flip(-1).transpose(0, 1).to(torch.complex128).contiguous()
                     P = self.pool[o + lay["P"]:o + lay["P"] + r.L * 4].view(torch.float32)
@@ -289,6 +307,103 @@ def _plain_music_executor():
 
 def PlainMusicExecutor(*a, **k):
     return _plain_music_executor()(*a, **k)
+
+
+def _time_frames(fn, n_max, budget_s, n_min=1):
+    """Run fn(i) for i = 0, 1, ... until budget_s seconds of it (at least
+    n_min, at most n_max calls); returns (calls, seconds)."""
+    n, t = 0, 0.0
+    while n < n_max and (n < n_min or t < budget_s):
+        t0 = time.perf_counter()
+        fn(n)
+        t += time.perf_counter() - t0
+        n += 1
+    return n, t
+
+
+CPU_MUSIC_CACHE = os.path.join(ROOT, "profiles", "cpu_oracle_plain_music_m1024_t2048.md")
+
+
+def _plain_music_frame(i):
+    """Seconds of standard MUSIC through the oracle on frame i, one thread."""
+    import fmsynth
+    import oracle
+    th0, dth, _ = fmsynth.grid(L_GRID)
+    fr = fmsynth.make_frame(M, T, K, SNR_DB, seed=9100 + i, angle_range=(-75.0, 75.0),
+                            min_sep=1.0)
+    t0 = time.perf_counter()
+    oracle.run_frame(fr.X, K, "music", th0, dth, L_GRID, threads=1)
+    return time.perf_counter() - t0
+
+
+def cpu_plain_music_c2(n_frames):
+    """Standard MUSIC (eq. (4): the oracle's full Jacobi eigendecomposition)
+    on n_frames frames of the bench workload's shape, each on one host core
+    (the frames run side by side in separate processes).  Minutes per frame:
+    run on its own (--cpu-plain-music N), its summary kept under profiles/,
+    which the default run reports."""
+    import concurrent.futures as cf
+    os.environ["FM_ORACLE_PROGRESS"] = "1"   # the oracle reports each Jacobi sweep
+    with cf.ProcessPoolExecutor(max_workers=n_frames) as ex:
+        times = list(ex.map(_plain_music_frame, range(n_frames)))
+    for i, t in enumerate(times):
+        log(f"plain MUSIC oracle frame {i}: {t:.1f} s on one core")
+    return {"frames": n_frames, "cores_per_frame": 1,
+            "seconds_per_frame": [round(t, 2) for t in times],
+            "frames_per_s": round(n_frames / sum(times), 5)}
+
+
+def cpu_baseline(X, Om, idx, B, th0, dth):
+    """The FP64 oracle timed on this host (a reported baseline, not the
+    target): the headline on one core (the paper's timings are single-CPU
+    means), the same on all cores of the process, Method 1, the 100 frames
+    of the small plain-MUSIC configuration, and the cached standard-MUSIC
+    figure at this workload."""
+    import fmsynth
+    import oracle
+    thr = oracle.default_threads()
+    Xh = [X[i].cpu().numpy() for i in range(min(B, 16))]
+    Omh = [Om[i].cpu().numpy() for i in range(min(B, 16))]
+
+    def m2(threads):
+        return lambda i: oracle.run_frame(Xh[i % len(Xh)], K, "project", th0, dth, L_GRID,
+                                          Omega=Omh[i % len(Omh)], q=Q_ITERS, threads=threads)
+    n1, t1 = _time_frames(m2(1), 16, 8.0, n_min=2)
+    log(f"CPU oracle Method 2: {n1 / t1:.4f} frames/s on 1 core ({n1} frames)")
+    nn, tn = _time_frames(m2(thr), 16, 4.0, n_min=3)
+    log(f"CPU oracle Method 2: {nn / tn:.4f} frames/s on {thr} threads ({nn} frames)")
+    nm1, tm1 = _time_frames(
+        lambda i: oracle.run_frame(Xh[i % len(Xh)], K, "sample", th0, dth, L_GRID,
+                                   idx=idx[i % len(idx)], threads=thr), 16, 3.0, n_min=3)
+    log(f"CPU oracle Method 1: {nm1 / tm1:.4f} frames/s on {thr} threads ({nm1} frames)")
+    # the small configuration: M = 64, T = 128, K = 3, 1801 angles, 100 frames
+    c1 = fmsynth.CONFIGS["c1"]
+    th1, dth1, L1 = fmsynth.grid(c1["L"])
+    frames1 = [fmsynth.config_frame("c1", seed=5000 + i)[0] for i in range(100)]
+    small = {"frames": 100, "cores": 1}
+    for name, kw in (("plain_music", {}),
+                     ("method1", {"idx": fmsynth.make_idx(c1["M"], c1["p"], 1)}),
+                     ("method2", {"Omega": fmsynth.make_omega(c1["M"], c1["l"], 1),
+                                  "q": c1["q"]})):
+        variant = {"plain_music": "music", "method1": "sample", "method2": "project"}[name]
+        t0 = time.perf_counter()
+        for fr in frames1:
+            oracle.run_frame(fr.X, c1["K"], variant, th1, dth1, L1, threads=1, **kw)
+        small[f"{name}_frames_per_s"] = round(100 / (time.perf_counter() - t0), 2)
+    log(f"CPU oracle, M=64 frames: {small}")
+    cached = None
+    if os.path.exists(CPU_MUSIC_CACHE):
+        m = re.search(r"frames_per_s:\s*([0-9.eE+-]+)", open(CPU_MUSIC_CACHE).read())
+        if m:
+            cached = {"frames_per_s": float(m.group(1)), "cores": 1,
+                      "source": os.path.relpath(CPU_MUSIC_CACHE, ROOT)}
+    return {"value": round(n1 / t1, 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n1} frame(s) of the same workload through the FP64 oracle on one "
+                      "host core (covariance, Method 2, spectrum, peaks)",
+            "all_cores": {"value": round(nn / tn, 4), "cores": thr, "frames": nn},
+            "method1_all_cores": {"value": round(nm1 / tm1, 4), "cores": thr, "frames": nm1},
+            "config1_m64": small,
+            "plain_music_one_core": cached}
 
 
 def main():
@@ -315,10 +430,16 @@ def main():
                     help="timed graph launches of the 512-frame uneven batch (0 = skip)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file to store the autotuner's choices in")
+    ap.add_argument("--cpu-plain-music", type=int, default=0, metavar="N",
+                    help="only time N standard-MUSIC oracle frames of the workload on one "
+                         "host core (minutes each) and print them as JSON")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
     legs = set() if args.no_extra else {x for x in args.legs.split(",") if x}
+    if args.cpu_plain_music > 0:
+        print(json.dumps(cpu_plain_music_c2(args.cpu_plain_music)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no "
               "multi-GPU form (one process drives one GPU)", file=sys.stderr)
@@ -683,26 +804,7 @@ def main():
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample -----------------
     if not args.no_cpu:
-        import oracle
-        thr = oracle.default_threads()
-        # frames of the timed batch, one after another, until about 10 s of
-        # oracle time (at most 64 frames)
-        frames_cpu, t_cpu = 0, 0.0
-        for i in range(min(64, B)):
-            Xh = X[i].cpu().numpy()
-            Omh = Om[i].cpu().numpy()
-            t0 = time.perf_counter()
-            oracle.run_frame(Xh, K, "project", th0, dth, L_GRID, Omega=Omh, q=Q_ITERS,
-                             threads=thr)
-            t_cpu += time.perf_counter() - t0
-            frames_cpu += 1
-            if t_cpu >= 10.0:
-                break
-        out["cpu_baseline"] = {"value": round(frames_cpu / t_cpu, 4), "unit": "frames/s",
-                               "cores": thr, "kind": "oracle",
-                               "sample": f"{frames_cpu} frame(s) of the same workload through "
-                                         "the FP64 oracle (covariance, Method 2, spectrum, peaks)"}
-        log(f"CPU oracle: {frames_cpu / t_cpu:.4f} frames/s on {thr} threads")
+        out["cpu_baseline"] = cpu_baseline(X, Om, idx, B, th0, dth)
 
     print(json.dumps(out), flush=True)
     ctx.close()

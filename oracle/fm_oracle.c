@@ -37,6 +37,7 @@
  *    lower index.
  */
 #include <complex.h>
+#include <stdio.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -124,6 +125,12 @@ static int jacobi_eigh(zc *A, int n, double *w, zc *V, int max_sweeps) {
       }
     if (off <= 1e-30 * tot || off == 0.0) { done = 1; break; }
     if (sweep == max_sweeps) break;
+    if (n >= 512 && getenv("FM_ORACLE_PROGRESS")) {
+      /* long solves report each sweep (timing runs that must show progress) */
+      fprintf(stderr, "oracle: Jacobi n=%d sweep %d, off-diagonal/total %.3g\n", n, sweep,
+              off / tot);
+      fflush(stderr);
+    }
     for (int p = 0; p < n - 1; ++p)
       for (int q = p + 1; q < n; ++q) {
         zc b = A[(size_t)p * n + q];

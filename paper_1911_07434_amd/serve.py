@@ -1,13 +1,14 @@
 """Continuous-batching serving loop for radar frames on one GPU.
 
 Frames (radar snapshot matrices of different M, T, K) arrive over time.  The
-server keeps each frame's snapshots, covariance, subspace and spectrum on
-the device, admits frames against an HBM budget, and whenever one of its
-streams is idle it launches the frames that have arrived as one batch (one
-fm_plan built in pool memory with fm_plan_create_in: nothing is allocated or
-synchronised per batch).  Batches on different streams overlap on the
-device; a frame that arrives while others run is picked up by the next idle
-stream.  Latency = completion of the frame's batch on the GPU - arrival.
+server admits frames against an HBM budget that counts each frame's own
+snapshots, covariance, subspace and spectrum (all kept on the device, in one
+pool), and whenever one of its streams is idle it launches the frames that
+have arrived as one batch (one fm_plan built in pool memory with
+fm_plan_create_in: nothing is allocated or synchronised per batch).  Batches
+on different streams overlap on the device; a frame that arrives while
+others run is picked up by the next idle stream.  Latency = completion of
+the frame's batch on the GPU - arrival.
 
 The scheduler (Server) is independent of the GPU: it talks to an executor
 (launch / poll / release) and a clock, so the CPU tests drive it with a
@@ -175,6 +176,9 @@ class ServeStats:
     max_inflight_bytes: int
     max_concurrent_batches: int
     mean_batch: float
+    mean_inflight_bytes: float = 0.0
+    admission_wait_ms: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    quarantined_bytes: int = 0
     extra: dict = field(default_factory=dict)
 
     def summary(self) -> dict:
@@ -189,7 +193,13 @@ class ServeStats:
             "max_ms": round(float(np.max(lat)), 3) if lat.size else None,
             "batches": self.batches, "mean_batch": round(self.mean_batch, 2),
             "max_concurrent_batches": self.max_concurrent_batches,
-            "max_inflight_bytes": self.max_inflight_bytes, **self.extra,
+            "max_inflight_bytes": self.max_inflight_bytes,
+            "mean_inflight_bytes": int(self.mean_inflight_bytes),
+            "admission_wait_p50_ms": (round(float(np.percentile(self.admission_wait_ms, 50)), 3)
+                                      if self.admission_wait_ms.size else None),
+            "admission_wait_p99_ms": (round(float(np.percentile(self.admission_wait_ms, 99)), 3)
+                                      if self.admission_wait_ms.size else None),
+            "quarantined_bytes": self.quarantined_bytes, **self.extra,
         }
 
 
@@ -257,8 +267,12 @@ class Server:
         max_conc = 0
         max_bytes = 0
         last_progress = self.clock.now()
+        quarantined = 0
+        t_prev, used_time = last_progress, 0.0   # time integral of the pool's use
         while nxt < len(reqs) or queue or inflight:
             now = self.clock.now()
+            used_time += self.pool.used * (now - t_prev)
+            t_prev = now
             progress = False
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
                 queue.append(reqs[nxt])
@@ -315,12 +329,17 @@ class Server:
                 last_progress = now
             else:
                 if inflight and now - last_progress > self.stall_timeout_s:
-                    # watchdog: the device made no progress; give up on these batches
+                    # watchdog: the device made no progress; give up on these
+                    # batches.  Their kernels may still write into their frame
+                    # and plan memory, so that memory is quarantined (never
+                    # handed out again in this run), not freed.
                     for s, b in list(inflight.items()):
                         for r in b.reqs:
                             r.status = "failed"
-                            self._release(r)
-                        self.pool.free(*b.plan_mem)
+                            if r.mem:
+                                quarantined += r.mem[1]
+                                r.mem = ()
+                        quarantined += b.plan_mem[1]
                         del inflight[s]
                     last_progress = now
                     continue
@@ -331,15 +350,19 @@ class Server:
                 self.clock.idle(hint)
         done = [r for r in reqs if r.status == "done"]
         lat = np.array([(r.done - r.arrival) * 1e3 for r in done])
+        wait = np.array([(r.admitted - r.arrival) * 1e3 for r in done])
         end = max((r.done for r in done), default=0.0)
         start = reqs[0].arrival if reqs else 0.0
+        span = self.clock.now() - (reqs[0].arrival if reqs else 0.0)
         return ServeStats(
             latencies_ms=lat, completed=len(done),
             failed=sum(r.status == "failed" for r in reqs),
             rejected=sum(r.status == "rejected" for r in reqs),
             duration_s=max(end - start, 1e-9), batches=len(sizes),
             max_inflight_bytes=max_bytes, max_concurrent_batches=max_conc,
-            mean_batch=float(np.mean(sizes)) if sizes else 0.0)
+            mean_batch=float(np.mean(sizes)) if sizes else 0.0,
+            mean_inflight_bytes=used_time / span if span > 0 else 0.0,
+            admission_wait_ms=wait, quarantined_bytes=quarantined)
 
 
 # --------------------------------------------------------------------------
@@ -349,15 +372,19 @@ class Server:
 class GpuExecutor:
     """Runs batches through libfastmusic plans built in a device memory pool.
 
-    Snapshot data come from a pool of device-resident frames, one per M
-    class, T_max snapshots long, K_max sources; a request uses the first T
-    snapshots (leading dimension T_max) of its class's frame.  Gaussian test
-    matrices are drawn once per (M, l) and shared.
+    Each admitted frame gets its own snapshot matrix X (complex64 [M][T]) in
+    its pool memory, generated on the device when its batch is launched (on
+    the batch's stream, so it counts in the frame's latency): K sources at
+    angles drawn uniformly in [-75, 75] deg, unit-power CN(0, 1) source
+    signals and CN(0, sigma^2) noise at the frame's own SNR, X = A S + N
+    (the signal model of fmsynth), from a device generator seeded by the
+    request id -- so a frame's data do not depend on what it is batched
+    with.  Gaussian test matrices are drawn once
+    per (M, l) and shared.
     """
 
-    def __init__(self, ctx, pool_bytes: int, n_streams: int = 2, T_max: int = 4096,
-                 K_src: int = 32, Ms=(128, 256, 512, 1024, 2048, 4096), seed: int = 7,
-                 prec: int = 0, keep_results: bool = False):
+    def __init__(self, ctx, pool_bytes: int, n_streams: int = 2, seed: int = 7,
+                 prec: int = 0, keep_results: bool = False, **_ignored):
         import torch
 
         import fmsynth
@@ -366,16 +393,13 @@ class GpuExecutor:
         self.fm_pkg = __import__("paper_1911_07434_amd")
         self.ctx = ctx
         self.prec = prec
+        self.seed = int(seed)
         self.rcond = FM_RCOND_DEFAULT
         self.keep_results = keep_results
         self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
         self.base = self.pool.data_ptr()
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
-        self.T_max = T_max
-        self.X = {}
-        for i, M in enumerate(Ms):
-            X, _ = fmsynth.make_batch_device(M, T_max, min(K_src, M - 1), 10.0, 1, seed + i)
-            self.X[M] = X[0].contiguous()
+        self.gen = torch.Generator(device="cuda")
         self.omega = {}
         self.fmsynth = fmsynth
         self.t0_event = torch.cuda.Event(enable_timing=True)
@@ -389,6 +413,27 @@ class GpuExecutor:
         self.t0_event.synchronize()
         self.t0_host = clock.now()
 
+    def make_X(self, req, out):
+        """Write request `req`'s snapshot matrix into `out` (complex64 [M][T],
+        contiguous) on the current stream.  Everything is drawn on the device
+        (no host-to-device copy, which would wait for the stream): K angles
+        uniform in [-75, 75] deg, the steering matrix A with the phase
+        m sin(theta) reduced mod 2 in FP64, S and N."""
+        torch = self.torch
+        M, T, K = req.M, req.T, req.K
+        dev = out.device
+        self.gen.manual_seed(self.seed * 1000003 + req.rid)
+        th = torch.rand(K, generator=self.gen, device=dev, dtype=torch.float64) * 150.0 - 75.0
+        x = torch.outer(torch.arange(M, device=dev, dtype=torch.float64),
+                        torch.sin(th * (np.pi / 180.0)))
+        x = x - 2.0 * torch.floor(x * 0.5)
+        A = torch.polar(torch.ones_like(x), -np.pi * x).to(torch.complex64)
+        z = torch.randn((2, M + K, T), generator=self.gen, device=dev)
+        S = torch.complex(z[0, M:], z[1, M:]) * np.float32(np.sqrt(0.5))
+        torch.matmul(A, S, out=out)
+        sig = np.float32(np.sqrt(10.0 ** (-req.snr_db / 10.0) / 2.0))
+        out.add_(torch.complex(z[0, :M], z[1, :M]), alpha=sig)
+
     def _omega(self, M, l):
         key = (M, l)
         if key not in self.omega:
@@ -398,8 +443,8 @@ class GpuExecutor:
     @staticmethod
     def _layout(req):
         M, K, L = req.M, req.K, req.L
-        parts = [("R", M * M * 8), ("Us", K * M * 16), ("sigma", K * 8), ("status", 4),
-                 ("P", L * 4), ("pidx", K * 4), ("pval", K * 4), ("nf", 4)]
+        parts = [("X", M * req.T * 8), ("R", M * M * 8), ("Us", K * M * 16), ("sigma", K * 8),
+                 ("status", 4), ("P", L * 4), ("pidx", K * 4), ("pval", K * 4), ("nf", 4)]
         off, lay = 0, {}
         for name, n in parts:
             lay[name] = off
@@ -422,8 +467,8 @@ class GpuExecutor:
         lay, _ = self._layout(req)
         base = self.base + req.mem[0] if req.mem else 0
         f = fm.fm_frame()
-        f.X = self.X[req.M].data_ptr()
-        f.ldx = self.T_max
+        f.X = base + lay["X"]
+        f.ldx = req.T
         f.M, f.T = req.M, req.T
         f.R = base + lay["R"]
         f.ldr = req.M
@@ -450,9 +495,18 @@ class GpuExecutor:
             raise RuntimeError(self.ctx.lib.fm_last_error(self.ctx.h).decode())
         return n
 
+    def X_view(self, req):
+        """The request's snapshot matrix in its pool memory."""
+        lay, _ = self._layout(req)
+        o = req.mem[0] + lay["X"]
+        return self.pool[o:o + req.M * req.T * 8].view(self.torch.complex64).view(req.M, req.T)
+
     def launch(self, reqs, stream_idx, plan_mem):
         fm = self.fm_pkg
         s = self.streams[stream_idx]
+        with self.torch.cuda.stream(s):
+            for r in reqs:
+                self.make_X(r, self.X_view(r))
         descs = [self._descriptor(r) for r in reqs]
         plan = fm.Plan(self.ctx, descs, prec=self.prec, dev_mem=self.base + plan_mem[0],
                        dev_bytes=plan_mem[1], stream=s)

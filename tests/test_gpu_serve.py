@@ -1,6 +1,7 @@
 """Serving on the GPU: frames that arrive while others run are batched
-continuously, and every frame's results are bit-identical to running it
-alone through the single-frame entry points."""
+continuously, each with its own snapshots generated into the pool, and
+every frame's results are bit-identical to running it alone (the same
+snapshots generated again, then the single-frame entry points)."""
 import numpy as np
 import pytest
 
@@ -27,7 +28,8 @@ def _unpack(raw, lay, req):
     def take(name, dtype, count):
         return np.frombuffer(b[lay[name]:lay[name] + count * np.dtype(dtype).itemsize].tobytes(),
                              dtype=dtype)
-    return dict(R=take("R", np.complex64, M * M).reshape(M, M),
+    return dict(X=take("X", np.complex64, M * req.T).reshape(M, req.T),
+                R=take("R", np.complex64, M * M).reshape(M, M),
                 Us=take("Us", np.complex128, K * M).reshape(K, M),
                 sigma=take("sigma", np.float64, K), status=int(take("status", np.int32, 1)[0]),
                 P=take("P", np.float32, L), n=int(take("nf", np.int32, 1)[0]),
@@ -38,8 +40,7 @@ def test_served_frames_equal_alone_bitwise(ctx):
     Ms = (128, 256, 512)
     reqs = poisson_arrivals(20000.0, 10.0, seed=3, Ms=Ms, T_range=(64, 512), K_range=(1, 12),
                             L=2001, max_frames=48)
-    ex = GpuExecutor(ctx, pool_bytes=1 << 30, n_streams=3, T_max=512, K_src=12, Ms=Ms,
-                     keep_results=True)
+    ex = GpuExecutor(ctx, pool_bytes=1 << 30, n_streams=3, keep_results=True)
     clock = WallClock()
     ex.start(clock)
     st = Server(ex, budget_bytes=1 << 30, n_streams=3, max_batch=8, clock=clock).run(reqs)
@@ -50,7 +51,8 @@ def test_served_frames_equal_alone_bitwise(ctx):
         raw, lay = ex.results[r.rid]
         got = _unpack(raw, lay, r)
         # the same frame alone
-        X = ex.X[r.M][:, :r.T]
+        X = torch.empty((r.M, r.T), dtype=torch.complex64, device="cuda")
+        ex.make_X(r, X)
         R = torch.empty((r.M, r.M), dtype=torch.complex64, device="cuda")
         Us = torch.zeros((r.K, r.M), dtype=torch.complex128, device="cuda")
         sig = torch.zeros(r.K, dtype=torch.float64, device="cuda")
@@ -60,6 +62,7 @@ def test_served_frames_equal_alone_bitwise(ctx):
         ctx.fm_subspace_project(R, ex._omega(r.M, r.n), r.q, r.K, Us, sig, sta)
         ctx.fm_pseudospectrum(Us, -90.0, 180.0 / (r.L - 1), r.L, P)
         torch.cuda.synchronize()
+        assert np.array_equal(got["X"], X.cpu().numpy()), r
         assert np.array_equal(got["R"], R.cpu().numpy()), r
         assert np.array_equal(got["Us"], Us.cpu().numpy()), r
         assert np.array_equal(got["sigma"], sig.cpu().numpy()), r

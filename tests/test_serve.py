@@ -158,7 +158,11 @@ def test_watchdog_gives_up_on_a_stalled_batch():
     st = srv.run(reqs)
     assert reqs[2].status == "failed"
     assert st.completed == 5
-    assert srv.pool.used == 0
+    # the stalled batch may still write its memory: quarantined, never reused
+    held = ex.frame_bytes(reqs[2]) + ex.plan_bytes([reqs[2]])
+    assert st.quarantined_bytes == held
+    assert srv.pool.used == held
+    assert st.summary()["quarantined_bytes"] == held
 
 
 def test_poisson_arrivals_population():
@@ -169,3 +173,26 @@ def test_poisson_arrivals_population():
     assert {r.M for r in reqs} == {128, 256, 512, 1024, 2048, 4096}
     assert min(r.T for r in reqs) >= 64 and max(r.T for r in reqs) <= 4096
     assert all(1 <= r.K <= 32 and r.n == min(r.K + 8, 40) for r in reqs)
+
+
+def test_budget_binding_run_reports_admission_waits():
+    # frames of 8 MiB each, 4 ms of work each, arriving every 1 ms on two
+    # streams: a budget of 3 frames (plus plans) makes arrivals wait
+    clk = VirtualClock()
+    ex = FakeExecutor(clk, per_frame_s=4e-3, plan_bytes=256)
+    reqs = reqs_uniform(40, 1e-3)
+    clk_free = VirtualClock()
+    free = Server(FakeExecutor(clk_free, per_frame_s=4e-3, plan_bytes=256),
+                  budget_bytes=1 << 40, n_streams=2, max_batch=4,
+                  clock=clk_free).run(reqs_uniform(40, 1e-3))
+    budget = 3 * (8 << 20) + 4096
+    srv = Server(ex, budget_bytes=budget, n_streams=2, max_batch=4, clock=clk)
+    st = srv.run(reqs)
+    s = st.summary()
+    assert st.completed == 40 and st.rejected == 0
+    assert st.max_inflight_bytes <= budget
+    assert 0 < st.mean_inflight_bytes <= budget
+    assert s["admission_wait_p99_ms"] > 0.0
+    # binding the budget delays admission relative to an unbounded run
+    assert np.percentile(st.admission_wait_ms, 99) > np.percentile(free.admission_wait_ms, 99)
+    assert srv.pool.used == 0
