@@ -579,8 +579,14 @@ def main():
         P_main = [frames2[i].P.double().cpu().numpy() for i in range(n_chk)]
         mixed = {}
         for pname, prec in (("fp16", fm.FM_FP16), ("bf16", fm.FM_BF16),
-                            ("fp16x3", fm.FM_FP16X3), ("bf16x3", fm.FM_BF16X3)):
-            planm = fm.Plan(ctx, [d.descriptor() for d in frames2], prec=prec)
+                            ("fp16x3", fm.FM_FP16X3), ("bf16x3", fm.FM_BF16X3),
+                            ("fp16+spec16", fm.FM_FP16)):
+            descs = [d.descriptor() for d in frames2]
+            if pname.endswith("+spec16"):
+                # the spectrum as the split hi + lo FP16 steering projection
+                for f in descs:
+                    f.spec_prec = fm.FM_FP16
+            planm = fm.Plan(ctx, descs, prec=prec)
             with torch.cuda.stream(stream):
                 step(planm)
                 torch.cuda.synchronize()
@@ -600,9 +606,9 @@ def main():
                             "covariance_tflops": round(am, 1),
                             "covariance_frac_of_16bit_peak": round(am / PEAK_F16_MFMA_TFLOPS, 4)}
             mixed[pname]["covariance_mfma_busy_frac"] = round(
-                B * cov_mfma_flops(M, T, pname) / (sm["covariance"] * 1e-3) / 1e12
+                B * cov_mfma_flops(M, T, pname.split("+")[0]) / (sm["covariance"] * 1e-3) / 1e12
                 / PEAK_F16_MFMA_TFLOPS, 4)
-            tr = pmc_traffic(B, pname)
+            tr = pmc_traffic(B, pname.split("+")[0])
             mixed[pname]["covariance_traffic_frac_of_hbm_peak"] = (
                 round(tr / (sm["covariance"] * 1e-3) / (PEAK_HBM_GBS * 1e9), 4) if tr else None)
             dP = max(float(np.max(np.abs(10 * np.log10(
@@ -616,8 +622,10 @@ def main():
                                        "16-bit hi+lo halves, three products, FP32-level "
                                        "error); Method 2 sketch on FP16 matrix cores "
                                        "with hi+lo split operands (three products, FP32 "
-                                       "accumulation); spectrum FP32 (polynomial pass); small "
-                                       "dense steps and peak-region denominators FP64")
+                                       "accumulation); spectrum FP32 (polynomial pass; "
+                                       "+spec16: split hi+lo FP16 steering projection on "
+                                       "matrix cores); small dense steps and peak-region "
+                                       "denominators FP64")
 
         # ---- Method 1 on the same frames -----------------------------------
         del plan2

@@ -77,8 +77,8 @@ typedef enum {
  *     twiddles into FP16 hi + lo halves and accumulates hi*hi + hi*lo +
  *     lo*hi (~22-bit products), K products per angle; FM_FP16X3 is the
  *     same pass.  fm_pseudospectrum rejects FM_BF16 and FM_BF16X3
- *     (FM_E_UNSUPPORTED).  Plans at every precision run the
- *     FP32 polynomial pass (faster and more accurate than the FP16 one).
+ *     (FM_E_UNSUPPORTED).  Plans run each frame's fm_frame.spec_prec pass
+ *     (default FM_FP32, the faster and more accurate of the two).
  *   sketch products Y = R V (fm_subspace_project, stage 2 of a plan):
  *     FM_FP32 uses FP32 products; every 16-bit precision splits R and V into
  *     FP16 hi + lo halves (power-of-two scaled) and accumulate hi*hi + hi*lo
@@ -388,6 +388,11 @@ typedef struct {
    * the subspace stage (K <= 32); null: none.  FM_ST_EIG_MAXIT is OR-ed
    * into status. */
   double *esprit_deg; /* double [K] */
+  /* pseudo-spectrum pass of this frame (as fm_pseudospectrum's prec):
+   * FM_FP32 (0, the default) the FP32 polynomial pass; FM_FP16 (or
+   * FM_FP16X3) the split hi + lo FP16 projection c_k = u_k^H a(theta) on the
+   * matrix cores.  Both recompute the peak-region denominators in FP64. */
+  int spec_prec;
 } fm_frame;
 
 /* Build a plan for n_frames frames (host array, copied): validates every
@@ -396,7 +401,7 @@ typedef struct {
  * frame is computed exactly as the single-frame entry points compute it:
  * fm_covariance and fm_subspace_project at the plan's precision `prec`,
  * fm_subspace_sample at FM_FP32,
- * fm_pseudospectrum at FM_FP32 for every plan. */
+ * fm_pseudospectrum at the frame's spec_prec. */
 fm_status fm_plan_create(fm_ctx *ctx, const fm_frame *frames, int n_frames, fm_prec prec,
                          fm_plan **out);
 /* Device bytes a plan for these frames needs (workspace, descriptors and

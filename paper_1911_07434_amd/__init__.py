@@ -65,6 +65,7 @@ class fm_frame(C.Structure):
         ("n_found", C.c_void_p),
         ("K_hat", C.c_void_p), ("order_crit", C.c_void_p), ("order_rule", C.c_int),
         ("esprit_deg", C.c_void_p),
+        ("spec_prec", C.c_int),
     ]
 
 

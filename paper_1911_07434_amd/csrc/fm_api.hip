@@ -100,7 +100,7 @@ struct fm_plan {
 namespace {
 
 enum Kind { kCov, kOmega, kGather, kSketch, kSketch16, kXhv, kXz, kZx, kXcore, kGram, kSmall, kApply,
-             kSpecPrep, kRefine, kPeaks, kOrder, kAcorr, kHsum, kPoly, kEsprit };
+             kSpecPrep, kRefine, kPeaks, kOrder, kAcorr, kHsum, kPoly, kEsprit, kSplit16, kSpec16 };
 
 fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
   if (ctx) {
@@ -696,6 +696,8 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kHsum: return fm::launch_hsum(cls, fr, it, L.count, s);
     case kPoly: return fm::launch_poly(cls, fr, it, L.count, L.mode, s);
     case kEsprit: return fm::launch_esprit(cls, fr, it, L.count, s);
+    case kSplit16: return fm::launch_split(cls, fr, it, L.count, s);
+    case kSpec16: return fm::launch_spectrum16(cls, fr, it, L.count, L.n_class, L.mode, s);
   }
   return hipErrorInvalidValue;
 }
@@ -736,6 +738,12 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
                      a.Us, a.sigma, a.status);
     if (st == FM_OK) st = check_spec(ctx, a.Us, a.M, a.K, a.theta0_deg, a.dtheta_deg, a.L, a.P);
     if (st == FM_OK) st = check_peaks(ctx, a.P, a.L, a.K, a.peak_idx, a.peak_val, a.n_found);
+    if (st == FM_OK && a.spec_prec != FM_FP32 && a.spec_prec != FM_FP16 &&
+        a.spec_prec != FM_FP16X3)
+      st = fail(ctx, a.spec_prec == FM_BF16 || a.spec_prec == FM_BF16X3 ? FM_E_UNSUPPORTED
+                                                                        : FM_E_ARG,
+                "plan: frame %d spectrum precision %d (FM_FP32 or FM_FP16 only)", i,
+                a.spec_prec);
     if (st == FM_OK && a.esprit_deg && a.K > fm::kEspritMaxK)
       st = fail(ctx, FM_E_UNSUPPORTED, "ESPRIT: K=%d > %d", a.K, fm::kEspritMaxK);
     if (st == FM_OK && a.K_hat) {
@@ -771,7 +779,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     off[i] = total;
     total += lay[i].total;
   }
-  // spectrum groups (every plan runs the FP32 polynomial pass): frames with equal M, angle grid and spectrum knob
+  // spectrum groups of the frames on the FP32 polynomial pass: frames with equal M, angle grid and spectrum knob
   // bucket, up to kPolyRows per group (in frame order), each with a group
   // buffer [M][kPolyRows] placed after the frames' workspaces
   std::vector<int> grp_of(n_frames, -1), slot_of(n_frames, 0);
@@ -780,6 +788,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   {
     std::map<std::tuple<int, int, uint64_t, uint64_t, int>, int> open;
     for (int i = 0; i < n_frames; ++i) {
+      if (frames[i].spec_prec != FM_FP32) continue;  // the FP16 projection pass needs no group
       uint64_t t0, dt;
       std::memcpy(&t0, &frames[i].theta0_deg, 8);
       std::memcpy(&dt, &frames[i].dtheta_deg, 8);
@@ -1058,8 +1067,9 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   add(p->spec, kSpecPrep, 0, 0, b0);
   b0 = begin();
   for (int i : order)
-    for (int c = 0; c < rows(frames[i].M, fm::kAcorrLags); ++c)
-      for (int b = 0; b < fm::acorr_blocks(frames[i].M); ++b) items.push_back({i, c, b, 0});
+    if (grp_of[i] >= 0)
+      for (int c = 0; c < rows(frames[i].M, fm::kAcorrLags); ++c)
+        for (int b = 0; b < fm::acorr_blocks(frames[i].M); ++b) items.push_back({i, c, b, 0});
   add(p->spec, kAcorr, 0, 0, b0);
   b0 = begin();
   for (const auto &g : groups)
@@ -1075,6 +1085,25 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     }
     add(p->spec, kPoly, per / 64, 0, b0);
   }
+  // frames on the split FP16 projection pass: U_s -> hi and lo FP16 planes
+  // (one workgroup per 256 entries), then one launch per column class nb and
+  // angle tile (64 nnb angles, the context's FM_KNOB_SPEC16_ANGLES)
+  auto spec16 = [&](int i) { return frames[i].spec_prec != FM_FP32; };
+  b0 = begin();
+  for (int i : order)
+    if (spec16(i))
+      for (int c = 0; c < rows(frames[i].K * frames[i].M, 256); ++c) items.push_back({i, c, 0, 0});
+  add(p->spec, kSplit16, 0, 0, b0);
+  for (int nb = 1; nb <= 8; ++nb)
+    for (int nnb : {4, 2, 1}) {
+      b0 = begin();
+      for (int i : order) {
+        if (!spec16(i) || std::min(spec_nb(frames[i].K), 8) != nb) continue;
+        if (ctx->knob[FM_KNOB_SPEC16_ANGLES][nb - 1] / 64 != nnb) continue;
+        for (int t = 0; t < rows(frames[i].L, 64 * nnb); ++t) items.push_back({i, t, 0, 0});
+      }
+      add(p->spec, kSpec16, nnb, nb, b0);
+    }
   b0 = begin();
   for (int i : order)
     for (int g = 0; g < fm::kRefineGroups; ++g) items.push_back({i, g, 0, 0});

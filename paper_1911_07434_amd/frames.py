@@ -30,6 +30,7 @@ class FrameSpec:
     rcond: float = FM_RCOND_DEFAULT
     order_rule: int | None = None  # FM_ORDER_AIC / FM_ORDER_MDL: also estimate K (Sec. V-D)
     esprit: bool = False           # also the ESPRIT angles of U_s (K <= 32)
+    spec_prec: int = 0             # FM_FP32: polynomial pass; FM_FP16: split hi+lo projection
 
 
 class DeviceFrame:
@@ -91,6 +92,7 @@ class DeviceFrame:
             f.order_rule = s.order_rule
         if self.doa is not None:
             f.esprit_deg = self.doa.data_ptr()
+        f.spec_prec = s.spec_prec
         return f
 
     def results(self) -> dict:
@@ -112,7 +114,7 @@ def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
     """All four stages of one frame through the single-frame entry points, as
     a plan at precision `prec` runs them: the covariance and the Method 2
     sketch at `prec`, Method 1 and Method 2 from X (no covariance) in FP32,
-    the spectrum in FP32 (the polynomial pass every plan runs)."""
+    the spectrum at the frame's spec_prec (FP32: the polynomial pass)."""
     s = fr.spec
     if s.method == FM_METHOD_PROJECT_X:
         # Method 2 from the snapshots: no covariance (FP32 products)
@@ -127,7 +129,7 @@ def run_single(ctx, fr: DeviceFrame, prec=0, stream=None):
                                 prec, stream)
     elif s.method == FM_METHOD_SAMPLE:
         ctx.fm_subspace_sample(fr.R, fr.idx, s.K, fr.Us, fr.sigma, fr.status, s.rcond, stream)
-    ctx.fm_pseudospectrum(fr.Us, s.theta0_deg, s.dtheta_deg, s.L, fr.P, FM_FP32, stream)
+    ctx.fm_pseudospectrum(fr.Us, s.theta0_deg, s.dtheta_deg, s.L, fr.P, s.spec_prec, stream)
     ctx.fm_peaks(fr.P, s.K, fr.peak_idx, fr.peak_val, fr.n_found, stream)
 
 

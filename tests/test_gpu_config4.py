@@ -28,9 +28,13 @@ M, T, K, L_SK, Q, L = 4096, 8192, 16, 24, 2, 36001
 # (its status and AoA checks still run in the per-SNR test).  The split
 # precisions (hi + lo halves, three 16-bit products) carry FP32-level error
 # and are held to the FP32 bar at every SNR.
-BARS_DB = {"fp32": 1e-3, "fp16": 1e-2, "bf16": 1e-2, "fp16x3": 1e-3, "bf16x3": 1e-3}
+# "+spec16": the same covariance precision with the split hi + lo FP16
+# steering projection as the spectrum pass (fm_frame.spec_prec = FM_FP16)
+BARS_DB = {"fp32": 1e-3, "fp16": 1e-2, "bf16": 1e-2, "fp16x3": 1e-3, "bf16x3": 1e-3,
+           "fp32+spec16": 1e-3, "fp16+spec16": 1e-2}
 PRECS = (("fp32", fm.FM_FP32), ("fp16", fm.FM_FP16), ("bf16", fm.FM_BF16),
-         ("fp16x3", fm.FM_FP16X3), ("bf16x3", fm.FM_BF16X3))
+         ("fp16x3", fm.FM_FP16X3), ("bf16x3", fm.FM_BF16X3),
+         ("fp32+spec16", fm.FM_FP32), ("fp16+spec16", fm.FM_FP16))
 # the dB bar of this cell is asserted in its own strict-xfail test
 KNOWN_OVER_BAR = {("bf16", 30.0)}
 
@@ -56,12 +60,13 @@ def _run_snr(ctx, snr):
                             pair_center_sep=2.0)
     Om = fmsynth.make_omega(M, L_SK, seed)
     th0, dth, _ = fmsynth.grid(L)
-    spec = FrameSpec(M=M, T=T, K=K, method=fm.FM_METHOD_PROJECT, n=L_SK, q=Q, L=L,
-                     theta0_deg=th0, dtheta_deg=dth)
     X = torch.from_numpy(fr.X).cuda()
     Omd = torch.from_numpy(Om).cuda()
     got = {}
     for name, prec in PRECS:
+        spec = FrameSpec(M=M, T=T, K=K, method=fm.FM_METHOD_PROJECT, n=L_SK, q=Q, L=L,
+                         theta0_deg=th0, dtheta_deg=dth,
+                         spec_prec=fm.FM_FP16 if name.endswith("+spec16") else fm.FM_FP32)
         d = DeviceFrame(spec, X=X, rnd=Omd)
         plan = fm.Plan(ctx, [d.descriptor()], prec=prec)
         plan.run()

@@ -798,3 +798,41 @@ def test_nonfinite_snapshot_is_reported(ctx, prec):
         torch.cuda.synchronize()
         plan.close()
         assert int(good.status.cpu()[0]) == 0
+
+
+def test_plan_spec16_pass_equals_single_calls_bitwise(ctx):
+    # frames whose spectrum runs the split hi + lo FP16 projection inside a
+    # plan (fm_frame.spec_prec = FM_FP16), mixed with polynomial-pass frames,
+    # at FP32 and FP16 covariance: bit-identical to the single-frame calls
+    import dataclasses
+    frames = _mixed_frames(8, seed=19)
+    frames = [(dataclasses.replace(sp, spec_prec=fm.FM_FP16 if i % 2 == 0 else fm.FM_FP32), X, r)
+              for i, (sp, X, r) in enumerate(frames)]
+    for prec in (fm.FM_FP32, fm.FM_FP16):
+        alone = []
+        for spec, X, rnd in frames:
+            d = DeviceFrame(spec, X=torch.from_numpy(X), rnd=torch.from_numpy(rnd))
+            run_single(ctx, d, prec=prec)
+            torch.cuda.synchronize()
+            alone.append(d.results())
+        devs = [DeviceFrame(s, X=torch.from_numpy(X), rnd=torch.from_numpy(r))
+                for s, X, r in frames]
+        plan = fm.Plan(ctx, [d.descriptor() for d in devs], prec=prec)
+        plan.run(use_graph=True)
+        torch.cuda.synchronize()
+        for a, d in zip(alone, devs):
+            b = d.results()
+            assert np.array_equal(a["P"], b["P"]), d.spec
+            assert np.array_equal(a["peak_idx"], b["peak_idx"])
+        plan.close()
+
+
+def test_plan_rejects_bf16_spectrum_pass(ctx):
+    fr = fmsynth.make_frame(64, 64, 2, 10.0, seed=3)
+    spec = FrameSpec(M=64, T=64, K=2, n=8, L=181, theta0_deg=-90.0, dtheta_deg=1.0,
+                     spec_prec=fm.FM_BF16)
+    d = DeviceFrame(spec, X=torch.from_numpy(fr.X),
+                    rnd=torch.from_numpy(fmsynth.make_omega(64, 8, 3)))
+    with pytest.raises(fm.FmError) as e:
+        fm.Plan(ctx, [d.descriptor()])
+    assert e.value.status == fm.FM_E_UNSUPPORTED
