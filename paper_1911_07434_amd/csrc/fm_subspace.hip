@@ -753,6 +753,337 @@ __device__ void sort_desc(const double2 *A, int np, int n, int *perm, double *w)
   __syncthreads();
 }
 
+// 1 / x and 1 / sqrt(x), x > 0 finite: the hardware approximations refined
+// by two Newton steps (each squares the relative error), a handful of
+// dependent FMAs against the long correctly-rounded sequences
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ inline double rsq_nr(double x) {
+  const double h = 0.5 * x;
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  return r;
+}
+
+// Rotation of the pair (p, q) that annihilates b = A_pq, as in jacobi_eigh:
+// J = [[c, s], [-s e, c e]] with e = conj(b) / |b| and t = s / c the smaller
+// root of t^2 + 2 z t - 1 = 0, z = (A_qq - A_pp) / (2 |b|); mode 0 identity,
+// 1 rotate, 2 identity and zero A_pq (|b| negligible against the diagonal).
+// t starts in single precision and takes one Newton step in double (error
+// ~1e-14 relative, left in A_pq for the next sweep); c and e are exact to
+// double rounding, so J is unitary to that level whatever t is.
+struct RotW {
+  double c, s, ex, ey, ap, aq;
+  int mode;
+};
+__device__ inline RotW make_rot(double ap, double aq, double2 b) {
+  RotW R;
+  R.c = 1.0;
+  R.s = 0.0;
+  R.ex = 1.0;
+  R.ey = 0.0;
+  R.ap = ap;
+  R.aq = aq;
+  R.mode = 0;
+  const double ab2 = b.x * b.x + b.y * b.y;
+  if (ab2 > 0.0) {
+    if (ab2 <= 1e-36 * fabs(ap * aq)) {
+      R.mode = 2;
+    } else {
+      const double ia = rsq_nr(ab2);  // 1 / |b|
+      const double ab = ab2 * ia;
+      const double z = (aq - ap) * (0.5 * ia), az = fabs(z);
+      double t;
+      if (az < 1e18) {
+        const float zf = (float)az;
+        const float t0 = __builtin_amdgcn_rcpf(zf + __builtin_sqrtf(fmaf(zf, zf, 1.0f)));
+        double u = (double)t0;
+        const double f = fma(u, u + 2.0 * az, -1.0);
+        u = fma(-f, (double)__builtin_amdgcn_rcpf((float)(2.0 * (u + az))), u);
+        t = z >= 0.0 ? u : -u;
+      } else {
+        t = (z >= 0.0 ? 0.5 : -0.5) * rcp_nr(az);
+      }
+      const double c = rsq_nr(fma(t, t, 1.0));
+      R.c = c;
+      R.s = t * c;
+      R.ex = b.x * ia;
+      R.ey = -b.y * ia;
+      R.ap = ap - t * ab;
+      R.aq = aq + t * ab;
+      R.mode = 1;
+    }
+  }
+  return R;
+}
+
+// Cyclic Jacobi with the same round-robin ordering and stopping rule as
+// jacobi_eigh, on one wave, for a 16 x 16 matrix (ld 16; a smaller matrix
+// zero-padded: a rotation against a padding index is the identity, so the
+// padding stays zero and the leading block's result is unchanged).  Lane l
+// owns the 2x2 block (ki, kj) = (l / 8, l % 8) of the round's pairs and
+// rows ki, ki + 8 of V's columns of pair kj.  It forms the rotation of pair
+// kj from the round's A and takes that of pair ki from lane ki (whose kj is
+// ki) by a cross-lane read, so a round needs no rotation table and no
+// workgroup barrier.  The wave's LDS reads and writes are performed in
+// program order; the wavefront-scope fences keep the compiler from moving
+// them across the read / write split.  Call from all 64 lanes of one wave.
+__device__ __forceinline__ int rr16(int pos, int round) {
+  int x = pos - 1 + round;
+  x = x >= 15 ? x - 15 : x;
+  return pos == 0 ? 0 : 1 + x;
+}
+__device__ __forceinline__ int jacobi_wave16(double2 *A, double2 *V) {
+  const int l = threadIdx.x & 63, ki = l >> 3, kj = l & 7;
+  for (int sweep = 0;; ++sweep) {
+    double off = 0.0, tot = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = l + 64 * u;
+      const double2 v = A[e];
+      const double a2 = v.x * v.x + v.y * v.y;
+      tot += a2;
+      if ((e >> 4) != (e & 15)) off += a2;
+    }
+    // xor butterfly: both partners add the same two operands, so every lane
+    // ends with the same sums and the exit is uniform
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      tot += __shfl_xor(tot, o);
+    }
+    if (off == 0.0 || off <= 1e-30 * tot) return sweep;
+    if (sweep == kMaxSweeps) return -1;
+    for (int round = 0; round < 15; ++round) {
+      int pi = rr16(ki, round), qi = rr16(15 - ki, round);
+      int pj = rr16(kj, round), qj = rr16(15 - kj, round);
+      if (pi > qi) {
+        const int t = pi;
+        pi = qi;
+        qi = t;
+      }
+      if (pj > qj) {
+        const int t = pj;
+        pj = qj;
+        qj = t;
+      }
+      const double apj = A[pj * 17].x, aqj = A[qj * 17].x;
+      const double2 bj = A[pj * 16 + qj];
+      const double2 b00 = A[pi * 16 + pj], b01 = A[pi * 16 + qj];
+      const double2 b10 = A[qi * 16 + pj], b11 = A[qi * 16 + qj];
+      const double2 vp0 = V[ki * 16 + pj], vq0 = V[ki * 16 + qj];
+      const double2 vp1 = V[(ki + 8) * 16 + pj], vq1 = V[(ki + 8) * 16 + qj];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      const RotW Rj = make_rot(apj, aqj, bj);
+      // pair ki's rotation: lane ki computed it as its pair kj
+      RotW Ri;
+      Ri.c = __shfl(Rj.c, ki);
+      Ri.s = __shfl(Rj.s, ki);
+      Ri.ex = __shfl(Rj.ex, ki);
+      Ri.ey = __shfl(Rj.ey, ki);
+      Ri.ap = __shfl(Rj.ap, ki);
+      Ri.aq = __shfl(Rj.aq, ki);
+      Ri.mode = __shfl(Rj.mode, ki);
+      // J = [[c, s], [-s e, c e]]: qp = -s e, qq = c e of pair kj
+      const double qpx = -Rj.s * Rj.ex, qpy = -Rj.s * Rj.ey;
+      const double qqx = Rj.c * Rj.ex, qqy = Rj.c * Rj.ey;
+      // C = B J_j
+      auto colp = [&](double2 bp, double2 bq) {  // bp c + bq qp
+        return make_double2(fma(Rj.c, bp.x, fma(bq.x, qpx, -bq.y * qpy)),
+                            fma(Rj.c, bp.y, fma(bq.x, qpy, bq.y * qpx)));
+      };
+      auto colq = [&](double2 bp, double2 bq) {  // bp s + bq qq
+        return make_double2(fma(Rj.s, bp.x, fma(bq.x, qqx, -bq.y * qqy)),
+                            fma(Rj.s, bp.y, fma(bq.x, qqy, bq.y * qqx)));
+      };
+      const double2 c00 = colp(b00, b01), c01 = colq(b00, b01);
+      const double2 c10 = colp(b10, b11), c11 = colq(b10, b11);
+      // D = J_i^H C: J_i^H = [[c, -s conj(e)], [s, c conj(e)]]
+      const double2 w0 = make_double2(fma(Ri.ex, c10.x, Ri.ey * c10.y), fma(Ri.ex, c10.y, -Ri.ey * c10.x));
+      const double2 w1 = make_double2(fma(Ri.ex, c11.x, Ri.ey * c11.y), fma(Ri.ex, c11.y, -Ri.ey * c11.x));
+      double2 d00 = make_double2(fma(Ri.c, c00.x, -Ri.s * w0.x), fma(Ri.c, c00.y, -Ri.s * w0.y));
+      double2 d01 = make_double2(fma(Ri.c, c01.x, -Ri.s * w1.x), fma(Ri.c, c01.y, -Ri.s * w1.y));
+      double2 d10 = make_double2(fma(Ri.s, c00.x, Ri.c * w0.x), fma(Ri.s, c00.y, Ri.c * w0.y));
+      double2 d11 = make_double2(fma(Ri.s, c01.x, Ri.c * w1.x), fma(Ri.s, c01.y, Ri.c * w1.y));
+      if (ki == kj && Ri.mode != 0) {
+        // the pair's own 2x2 block: the rotated diagonal, A_pq annihilated
+        if (Ri.mode == 1) {
+          d00 = make_double2(Ri.ap, 0.0);
+          d11 = make_double2(Ri.aq, 0.0);
+        }
+        d01 = make_double2(0.0, 0.0);
+        d10 = d01;
+      }
+      A[pi * 16 + pj] = d00;
+      A[pi * 16 + qj] = d01;
+      A[qi * 16 + pj] = d10;
+      A[qi * 16 + qj] = d11;
+      V[ki * 16 + pj] = colp(vp0, vq0);
+      V[ki * 16 + qj] = colq(vp0, vq0);
+      V[(ki + 8) * 16 + pj] = colp(vp1, vq1);
+      V[(ki + 8) * 16 + qj] = colq(vp1, vq1);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+  }
+}
+
+// Hermitian eigen-solver of the small kernel: the one-wave Jacobi on the
+// 16 x 16 LDS matrices (wave 0 works, the others wait at the barrier), the
+// workgroup Jacobi for the wider classes.  Every thread returns the sweep
+// count.
+template <int NMAX>
+__device__ __forceinline__ int eigh_small(double2 *A, double2 *V, int np, Rot *rot, double *red,
+                                          int *sweeps) {
+  if constexpr (NMAX == 16) {
+    if (threadIdx.x < 64) {
+      const int sw = jacobi_wave16(A, V);
+      if (threadIdx.x == 0) *sweeps = sw;
+    }
+    __syncthreads();
+    return *sweeps;
+  } else {
+    return jacobi_eigh(A, V, np, rot, red);
+  }
+}
+
+// Cholesky factor of the leading n x n block of the Hermitian A (ld np) in
+// place, right-looking (step j updates the trailing lower triangle, one
+// entry per thread, then scales column j), and X = L^-1 (X must hold the
+// identity; lower triangle, ld np) by forward substitution, rows of X in
+// turn and columns in parallel.  inv[j] receives 1 / L_jj.  Returns false,
+// the same in every thread, when a pivot is not above kCholPivot * dmax (A
+// is then partly overwritten).  Two barriers per step.
+__device__ __forceinline__ bool chol_inv(double2 *A, double2 *X, double *inv, int np, int n, double dmax) {
+  for (int j = 0; j < n; ++j) {
+    const double d = A[j * np + j].x;
+    if (!(d > kCholPivot * dmax)) return false;
+    const double il = rsq_nr(d), rd = il * il;
+    const int m = n - 1 - j;
+    // A_ik -= A_ij conj(A_kj) / d on the trailing lower triangle
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k > i) continue;
+      const double2 aij = A[i * np + j], akj = A[k * np + j];
+      const double2 p = cmulc(akj, aij);  // A_ij conj(A_kj)
+      const double2 a = A[i * np + k];
+      A[i * np + k] = make_double2(a.x - p.x * rd, a.y - p.y * rd);
+    }
+    __syncthreads();
+    const double l = d * il;
+    for (int i = j + threadIdx.x; i < n; i += blockDim.x) {
+      const double2 a = A[i * np + j];
+      A[i * np + j] = i == j ? make_double2(l, 0.0) : make_double2(a.x * il, a.y * il);
+    }
+    if (threadIdx.x == 0) inv[j] = il;
+    __syncthreads();
+  }
+  // L X = I: row i of X is (B_i - sum_k<i L_ik X_k) / L_ii, with B_i kept
+  // in X's row i and the sum applied as rows of X are finished
+  for (int i = 0; i < n; ++i) {
+    const double il = inv[i];
+    for (int c = threadIdx.x; c <= i; c += blockDim.x) {
+      const double2 b = X[i * np + c];
+      X[i * np + c] = make_double2(b.x * il, b.y * il);
+    }
+    __syncthreads();
+    const int m = n - 1 - i;
+    for (int e = threadIdx.x; e < m * (i + 1); e += blockDim.x) {
+      const int k = i + 1 + e / (i + 1), c = e % (i + 1);
+      const double2 x = cmul(A[k * np + i], X[i * np + c]);
+      const double2 b = X[k * np + c];
+      X[k * np + c] = make_double2(b.x - x.x, b.y - x.y);
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// chol_inv on one wave for the 16 x 16 LDS matrices (ld 16), n <= 16: lane
+// l handles entries l + 64 u (u < 4), row (l >> 4) + 4 u, column l & 15.
+// Every step issues all its LDS reads unconditionally and selects the new
+// values branch-free, then writes; the wave's LDS accesses are performed in
+// program order, and wavefront-scope fences keep the compiler from moving
+// them across the read / write split.  Call from all 64 lanes of one wave;
+// the result is uniform.
+__device__ __forceinline__ bool chol_inv_wave16(double2 *A, double2 *X, double *inv, int n,
+                                                double dmax) {
+  const int l = threadIdx.x & 63, r0 = l >> 4, k = l & 15;
+  for (int j = 0; j < n; ++j) {
+    const double d = A[j * 17].x;
+    double2 a[4], aij[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = A[l + 64 * u];
+      aij[u] = A[(r0 + 4 * u) * 16 + j];
+    }
+    const double2 akj = A[k * 16 + j];
+    if (!(d > kCholPivot * dmax)) return false;
+    const double il = rsq_nr(d), rd = il * il;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = r0 + 4 * u;
+      // trailing entry (j < k <= i): A_ik - A_ij conj(A_kj) / d
+      const double px = aij[u].x * akj.x + aij[u].y * akj.y;
+      const double py = aij[u].y * akj.x - aij[u].x * akj.y;
+      const double2 t = make_double2(fma(-px, rd, a[u].x), fma(-py, rd, a[u].y));
+      // column j (i >= j): L_ij = A_ij / sqrt(d), L_jj = sqrt(d)
+      const double2 c = i == j ? make_double2(d * il, 0.0) : make_double2(a[u].x * il, a[u].y * il);
+      const bool live = i < n && k <= i;
+      const double2 v = !live ? a[u] : (k > j ? t : (k == j ? c : a[u]));
+      A[l + 64 * u] = v;
+    }
+    if (l == 0) inv[j] = il;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+  // L X = I, X holding the identity: at step i row i of X is scaled by
+  // 1 / L_ii (the rows above it applied) and applied to the rows below
+  for (int i = 0; i < n; ++i) {
+    const double il = inv[i];
+    double2 x[4], lk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = X[l + 64 * u];
+      lk[u] = A[(r0 + 4 * u) * 16 + i];
+    }
+    const double2 xi = X[i * 16 + k];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const double2 xs = make_double2(xi.x * il, xi.y * il);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = r0 + 4 * u;
+      const double2 t = make_double2(x[u].x - (lk[u].x * xs.x - lk[u].y * xs.y),
+                                     x[u].y - (lk[u].x * xs.y + lk[u].y * xs.x));
+      const bool live = k <= i && row < n && row >= i;
+      X[l + 64 * u] = !live ? x[u] : (row == i ? xs : t);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+  return true;
+}
+
+// chol_inv of the small kernel: on wave 0 for the 16 x 16 LDS matrices, by
+// the workgroup otherwise.  Uniform result in every thread.
+template <int NMAX>
+__device__ __forceinline__ bool chol_small(double2 *A, double2 *X, double *inv, int np, int n,
+                                           double dmax, int *flag) {
+  if constexpr (NMAX == 16) {
+    if (threadIdx.x < 64) {
+      const bool ok = chol_inv_wave16(A, X, inv, n, dmax);
+      if (threadIdx.x == 0) *flag = ok;
+    }
+    __syncthreads();
+    return *flag != 0;
+  } else {
+    return chol_inv(A, X, inv, np, n, dmax);
+  }
+}
+
 // LDS footprint of the small kernel for matrices up to NMAX (0: global).
 template <int NMAX>
 struct SmallLds {
@@ -770,31 +1101,53 @@ struct SmallLds {
   Rot rot[NMAX > 0 ? NMAX / 2 : kMaxN / 2];
   double red[256];
   double w[kMaxN];
+  double inv[kMaxN];
   int perm[kMaxN];
+  int sweeps;
+  int flag;
   int rank;
   unsigned st;
   int chol_ok;
 };
 
+// Entries (i, j) and (j, i) of the sum of a frame's Gram partials (slot
+// `which` of each chunk) in chunk order; the loads of eight chunks are issued
+// before their sums.
+__device__ inline void sum_parts(const double2 *part, int nchunk, int which, int n, int i, int j,
+                                 double2 &a, double2 &b) {
+  for (int c0 = 0; c0 < nchunk; c0 += 8) {
+    double2 va[8], vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = min(c0 + u, nchunk - 1);
+      const FM_GLOBAL double2 *pc =
+          (const FM_GLOBAL double2 *)(part + (size_t)(c * 2 + which) * n * n);
+      va[u] = pc[(size_t)i * n + j];
+      vb[u] = pc[(size_t)j * n + i];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (c0 + u < nchunk) {
+        a = cadd(a, va[u]);
+        b = cadd(b, vb[u]);
+      }
+  }
+}
+
 // Load a Hermitian matrix: sum of Gram partials (fixed chunk order) or a slot,
 // symmetrised, zero padded to np x np; V = I.
 __device__ void load_herm(double2 *A, double2 *V, int np, int n, const double2 *part,
-                          int nchunk, int which, const double2 *src) {
+                          int nchunk, int which, const double2 *src, int ldsrc) {
   for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
     const int i = e / np, j = e % np;
     double2 v = make_double2(0.0, 0.0);
     if (i < n && j < n) {
       double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
       if (part) {
-        for (int c = 0; c < nchunk; ++c) {
-          const FM_GLOBAL double2 *pc =
-              (const FM_GLOBAL double2 *)(part + (size_t)(c * 2 + which) * n * n);
-          a = cadd(a, pc[(size_t)i * n + j]);
-          b = cadd(b, pc[(size_t)j * n + i]);
-        }
+        sum_parts(part, nchunk, which, n, i, j, a, b);
       } else {
-        a = ((const FM_GLOBAL double2 *)src)[(size_t)i * np + j];
-        b = ((const FM_GLOBAL double2 *)src)[(size_t)j * np + i];
+        a = ((const FM_GLOBAL double2 *)src)[(size_t)i * ldsrc + j];
+        b = ((const FM_GLOBAL double2 *)src)[(size_t)j * ldsrc + i];
       }
       // (A + A^H) / 2
       v = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
@@ -811,68 +1164,24 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
   int unused_a, unused_b;
   const FrameDev &f = frame_of<kBatched>(single, frames, items, unused_a, unused_b);
   __shared__ SmallLds<NMAX> S;
-  const int n = f.n, np = f.npad;
+  // LDS matrices of the n <= 16 class are 16 x 16 (zero padding), the
+  // one-wave solvers' shape; the wider classes use the frame's even npad
+  const int n = f.n, np = NMAX == 16 ? 16 : f.npad;
   double2 *A = NMAX > 0 ? S.A : slot(f, kSlotA);
   double2 *V = NMAX > 0 ? S.V : slot(f, kSlotV);
   if (threadIdx.x == 0) S.st = 0u;
 
   if (mode == kOrth) {
-    load_herm(A, V, np, n, f.part, f.nchunk, 0, nullptr);
+    load_herm(A, V, np, n, f.part, f.nchunk, 0, nullptr, 0);
     double2 *T = slot(f, kSlotT);
-    // V_new = Y L^-H with Gram = L L^H (Cholesky, lower L in A's lower
-    // triangle).  Only span(V) matters downstream (the Nystrom approximation
-    // is the same for any basis of it); a small pivot -- an ill-conditioned
-    // or rank-deficient sketch -- falls back to the eigen route below.
+    // V_new = Y L^-H with Gram = L L^H (Cholesky, L^-1 in V).  Only span(V)
+    // matters downstream (the Nystrom approximation is the same for any basis
+    // of it); a small pivot -- an ill-conditioned or rank-deficient sketch --
+    // falls back to the eigen route below.
     {
       double dmax = 0.0;
       for (int i = 0; i < n; ++i) dmax = fmax(dmax, A[(size_t)i * np + i].x);
-      if (threadIdx.x == 0) S.chol_ok = dmax > 0.0;
-      __syncthreads();
-      for (int j = 0; j < n && S.chol_ok; ++j) {
-        if (threadIdx.x == 0) {
-          double d = A[(size_t)j * np + j].x;
-          for (int k = 0; k < j; ++k) {
-            const double2 l = A[(size_t)j * np + k];
-            d -= l.x * l.x + l.y * l.y;
-          }
-          if (!(d > kCholPivot * dmax)) S.chol_ok = 0;
-          else A[(size_t)j * np + j] = make_double2(sqrt(d), 0.0);
-        }
-        __syncthreads();
-        if (!S.chol_ok) break;
-        const double ljj = A[(size_t)j * np + j].x;
-        for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
-          double2 a = A[(size_t)i * np + j];
-          for (int k = 0; k < j; ++k) {
-            // a -= L[i][k] conj(L[j][k])
-            const double2 li = A[(size_t)i * np + k], lj = A[(size_t)j * np + k];
-            a = make_double2(a.x - (li.x * lj.x + li.y * lj.y), a.y - (li.y * lj.x - li.x * lj.y));
-          }
-          A[(size_t)i * np + j] = make_double2(a.x / ljj, a.y / ljj);
-        }
-        __syncthreads();
-      }
-      if (S.chol_ok) {
-        // T = L^-H: column c of L^-1 by forward substitution (one thread per
-        // column), written conjugate-transposed
-        for (int c = threadIdx.x; c < n; c += blockDim.x) {
-          for (int i = 0; i < n; ++i) {
-            double2 x = make_double2(i == c ? 1.0 : 0.0, 0.0);
-            if (i >= c) {
-              for (int k = c; k < i; ++k) {
-                const double2 l = A[(size_t)i * np + k];
-                const double2 y = V[(size_t)k * np + c];  // L^-1 column c, rows < i
-                x = make_double2(x.x - (l.x * y.x - l.y * y.y), x.y - (l.x * y.y + l.y * y.x));
-              }
-              const double lii = A[(size_t)i * np + i].x;
-              x = make_double2(x.x / lii, x.y / lii);
-            } else {
-              x = make_double2(0.0, 0.0);
-            }
-            V[(size_t)i * np + c] = x;
-          }
-        }
-        __syncthreads();
+      if (dmax > 0.0 && chol_small<NMAX>(A, V, S.inv, np, n, dmax, &S.flag)) {
         for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
           const int i = e / n, k = e % n;  // T[i][k] = conj(Linv[k][i])
           const double2 x = V[(size_t)k * np + i];
@@ -882,10 +1191,10 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
       }
       // the failed attempt overwrote A: reload the Gram for the eigen route
       if (threadIdx.x == 0) *wstat_of(f) |= FM_ST_ORTH_FALLBACK;
-      load_herm(A, V, np, n, f.part, f.nchunk, 0, nullptr);
+      load_herm(A, V, np, n, f.part, f.nchunk, 0, nullptr, 0);
     }
     // V_new = Y E diag(lambda^-1/2): orthonormal basis of the sketch
-    const int sw = jacobi_eigh(A, V, np, S.rot, S.red);
+    const int sw = eigh_small<NMAX>(A, V, np, S.rot, S.red, &S.sweeps);
     sort_desc(A, np, n, S.perm, S.w);
     const double thr = kRcondOrth * S.w[0];
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
@@ -913,12 +1222,7 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
     double2 v = make_double2(0.0, 0.0);
     if (i < n && j < n) {
       double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-      for (int c = 0; c < f.nchunk; ++c) {
-        const FM_GLOBAL double2 *pc =
-            (const FM_GLOBAL double2 *)(f.part + (size_t)(c * 2 + 1) * n * n);
-        a = cadd(a, pc[(size_t)i * n + j]);
-        b = cadd(b, pc[(size_t)j * n + i]);
-      }
+      sum_parts(f.part, f.nchunk, 1, n, i, j, a, b);
       v = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
       // a NaN or Inf anywhere in X or R reaches every entry of the sketch's
       // (or the sampled columns') Gram matrix
@@ -926,37 +1230,78 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
     }
     Gc[e] = v;
   }
-  if (sample) load_herm(A, V, np, n, nullptr, 0, 0, slot(f, kSlotCore));
-  else load_herm(A, V, np, n, f.part, f.nchunk, 0, nullptr);
-  int sw = jacobi_eigh(A, V, np, S.rot, S.red);
-  if (threadIdx.x == 0 && sw < 0) S.st |= FM_ST_EIG_MAXIT;
-  sort_desc(A, np, n, S.perm, S.w);
-  if (threadIdx.x == 0) {
-    const double thr = f.rcond * S.w[0];
-    int r = 0;
-    for (int k = 0; k < n; ++k)
-      if (S.w[k] > thr && S.w[k] > 0.0) ++r;
-    S.rank = r;
-    // the pseudo-inverse of eq. (8) dropped directions of the core
-    if (r < n) S.st |= FM_ST_CORE_TRUNCATED;
-    if (!isfinite(S.w[0])) S.st |= FM_ST_NONFINITE;
-  }
-  __syncthreads();
-  const int r1 = S.rank;
-  const int rp = (r1 + 1) & ~1;
-  // P = E_r diag(lambda^-1/2)   (n x r1, ld np)
+  auto load_core = [&]() {
+    if (sample) load_herm(A, V, np, n, nullptr, 0, 0, slot(f, kSlotCore), f.npad);
+    else load_herm(A, V, np, n, f.part, f.nchunk, 0, nullptr, 0);
+  };
+  load_core();
   double2 *P = kProdLds ? S.P : slot(f, kSlotP);
-  for (int e = threadIdx.x; e < n * np; e += blockDim.x) {
-    const int i = e / np, k = e % np;
-    double2 v = make_double2(0.0, 0.0);
-    if (k < r1) {
-      const double sc = 1.0 / sqrt(S.w[k]);
-      const double2 x = V[(size_t)i * np + S.perm[k]];
-      v = make_double2(x.x * sc, x.y * sc);
+  // P with P P^H = core^+ (eq. (8)).  Cholesky route: core = L L^H and
+  // P = L^-H, taken when the bounds lambda_min >= 1 / ||L^-1||_F^2 and
+  // lambda_max <= trace show that the pseudo-inverse's threshold keeps every
+  // direction (then core^+ = core^-1 exactly); otherwise the eigen route
+  // P = E_r diag(lambda^-1/2) over the kept eigenpairs.
+  bool chol = false;
+  {
+    double dmax = 0.0, tr = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double d = A[(size_t)i * np + i].x;
+      dmax = fmax(dmax, d);
+      tr += d;
     }
-    P[e] = v;
+    if (dmax > 0.0 && chol_small<NMAX>(A, V, S.inv, np, n, dmax, &S.flag)) {
+      double nrm = 0.0, unused = 0.0;
+      for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e / n, c = e % n;
+        const double2 x = V[(size_t)i * np + c];
+        if (c <= i) nrm += x.x * x.x + x.y * x.y;
+      }
+      block_sum2(nrm, unused, S.red);
+      // (false for NaN: such a core takes the eigen route, which reports it)
+      chol = nrm * tr * f.rcond < 0.5;
+    }
   }
-  __syncthreads();
+  int sw = 0;
+  if (chol) {
+    for (int e = threadIdx.x; e < n * np; e += blockDim.x) {
+      const int i = e / np, k = e % np;
+      const double2 x = k < n ? V[(size_t)k * np + i] : make_double2(0.0, 0.0);
+      P[e] = make_double2(x.x, -x.y);
+    }
+    if (threadIdx.x == 0) S.rank = n;
+    __syncthreads();
+  } else {
+    load_core();
+    sw = eigh_small<NMAX>(A, V, np, S.rot, S.red, &S.sweeps);
+    if (threadIdx.x == 0 && sw < 0) S.st |= FM_ST_EIG_MAXIT;
+    sort_desc(A, np, n, S.perm, S.w);
+    if (threadIdx.x == 0) {
+      const double thr = f.rcond * S.w[0];
+      int r = 0;
+      for (int k = 0; k < n; ++k)
+        if (S.w[k] > thr && S.w[k] > 0.0) ++r;
+      S.rank = r;
+      // the pseudo-inverse of eq. (8) dropped directions of the core
+      if (r < n) S.st |= FM_ST_CORE_TRUNCATED;
+      if (!isfinite(S.w[0])) S.st |= FM_ST_NONFINITE;
+    }
+    __syncthreads();
+    const int rk = S.rank;
+    // P = E_r diag(lambda^-1/2)   (n x r1, ld np)
+    for (int e = threadIdx.x; e < n * np; e += blockDim.x) {
+      const int i = e / np, k = e % np;
+      double2 v = make_double2(0.0, 0.0);
+      if (k < rk) {
+        const double sc = 1.0 / sqrt(S.w[k]);
+        const double2 x = V[(size_t)i * np + S.perm[k]];
+        v = make_double2(x.x * sc, x.y * sc);
+      }
+      P[e] = v;
+    }
+    __syncthreads();
+  }
+  const int r1 = S.rank;
+  const int rp = NMAX == 16 ? 16 : (r1 + 1) & ~1;
   // Z = Gc P  (n x r1)
   double2 *Z = kProdLds ? S.Z : slot(f, kSlotZ);
   for (int e = threadIdx.x; e < n * r1; e += blockDim.x) {
@@ -988,7 +1333,7 @@ __global__ __launch_bounds__(256) void small_kernel(FrameDev single, const Frame
   }
   __syncthreads();
   if (rp > 0) {
-    sw = jacobi_eigh(A, V, rp, S.rot, S.red);
+    sw = eigh_small<NMAX>(A, V, rp, S.rot, S.red, &S.sweeps);
     if (threadIdx.x == 0 && sw < 0) S.st |= FM_ST_EIG_MAXIT;
     sort_desc(A, rp, r1, S.perm, S.w);
   }
