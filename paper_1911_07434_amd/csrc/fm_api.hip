@@ -99,7 +99,7 @@ struct fm_plan {
 
 namespace {
 
-enum Kind { kCov, kOmega, kGather, kSketch, kSketch16, kXhv, kXz, kZx, kXcore, kGram, kSmall, kApply,
+enum Kind { kCov, kCovSplit, kOmega, kGather, kSketch, kSketch16, kXhv, kXz, kZx, kXcore, kGram, kSmall, kApply,
              kSpecPrep, kRefine, kPeaks, kOrder, kAcorr, kHsum, kPoly, kEsprit, kSplit16, kSpec16 };
 
 fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
@@ -119,6 +119,12 @@ fm_status hip_fail(fm_ctx *ctx, hipError_t e, const char *where) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// A plan runs the FP32 covariance's T segments on separate waves when its
+// one-wave blocks number fewer than this (two per SIMD on 1024 SIMDs)
+constexpr long long kCovSplitWaves = 2048;
+// ... and their segment sums fit in this much workspace
+constexpr size_t kCovSplitBytes = (size_t)64 << 20;
 
 // per-frame workspace layout (shared by single-frame calls and plans)
 struct WsLayout {
@@ -402,6 +408,17 @@ FM_API fm_status fm_covariance(fm_ctx *ctx, void *stream, const void *X, int M, 
   f.T = T;
   f.R = static_cast<float2 *>(R);
   f.ldr = ldr;
+  // FP32 with several T segments: one wave per segment and an in-order
+  // reduction when the context's arena holds the segment sums (the same
+  // bits as one wave running the segments in turn, four times the waves)
+  const size_t part_bytes = (size_t)fm::cov_units(M, FM_FP32) * fm::cov_segments(M, T) *
+                            fm::kCovPartFloats * sizeof(float);
+  if (prec == FM_FP32 && fm::cov_segments(M, T) > 1 && part_bytes <= ctx->arena_bytes) {
+    f.cpart = reinterpret_cast<float *>(ctx->arena);
+    FM_CHECK_LAUNCH(ctx, fm::launch_covariance_split(f, nullptr, nullptr, 0, 0, (hipStream_t)stream));
+    FM_CHECK_LAUNCH(ctx, fm::launch_covariance_split(f, nullptr, nullptr, 0, 1, (hipStream_t)stream));
+    return FM_OK;
+  }
   FM_CHECK_LAUNCH(ctx, fm::launch_covariance(f, nullptr, nullptr, 0, prec, (hipStream_t)stream));
   return FM_OK;
 }
@@ -677,6 +694,7 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
   const FrameDev *fr = p->frames_d;
   switch (L.kind) {
     case kCov: return fm::launch_covariance(cls, fr, it, L.count, p->prec, s);
+    case kCovSplit: return fm::launch_covariance_split(cls, fr, it, L.count, L.mode, s);
     case kOmega: return fm::launch_omega(cls, fr, it, L.count, 0, s);
     case kGather: return fm::launch_gather(cls, fr, it, L.count, s);
     case kSketch: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, L.mode, s);
@@ -809,6 +827,32 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
       total += align256((size_t)fm::acorr_blocks(Mg) * Mg * fm::kPolyRows * 8);
     }
   }
+  // FP32 covariance with its T segments on separate waves when the plan's
+  // one-wave blocks would not fill the GPU (same bits as the sequential
+  // segments); the segment sums follow the other workspaces
+  auto forms_r = [&](int i) {
+    return frames[i].method != FM_METHOD_PROJECT_X && frames[i].method != FM_METHOD_SAMPLE_X;
+  };
+  bool cov_split = false;
+  std::vector<size_t> coff(n_frames, 0);
+  if (prec == FM_FP32) {
+    long long waves = 0;
+    bool segs = false;
+    for (int i = 0; i < n_frames; ++i)
+      if (forms_r(i)) {
+        waves += fm::cov_units(frames[i].M, FM_FP32);
+        segs |= fm::cov_segments(frames[i].M, frames[i].T) > 1;
+      }
+    size_t cbytes = 0;
+    for (int i = 0; i < n_frames; ++i)
+      if (forms_r(i)) {
+        coff[i] = total + cbytes;
+        cbytes += align256((size_t)fm::cov_units(frames[i].M, FM_FP32) *
+                           fm::cov_segments(frames[i].M, frames[i].T) * fm::kCovPartFloats * sizeof(float));
+      }
+    cov_split = segs && waves < kCovSplitWaves && cbytes <= kCovSplitBytes;
+    if (cov_split) total += cbytes;
+  }
   p->ws_bytes = total;
   hipError_t e = hipSuccess;
   if (dry_run) {
@@ -855,6 +899,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     f.doa = a.esprit_deg;
     f.or_status = 1;
     bind_ws(f, p->ws + off[i], lay[i]);
+    if (cov_split && forms_r(i)) f.cpart = reinterpret_cast<float *>(p->ws + coff[i]);
     if (grp_of[i] >= 0) {
       f.hgrp = reinterpret_cast<float2 *>(p->ws + goff[grp_of[i]]);
       f.hslot = slot_of[i];
@@ -901,19 +946,37 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
       const int cb = cov_bucket(frames[i].M);
       int sched = ctx->knob[FM_KNOB_COV_SCHEDULE][cb];
       if (sched == 2) sched = (prec == FM_FP32 && cb >= 4) ? 1 : 0;
-      if (sched == 0) {
+      // split: each FP32 block once per T segment (Item::c = segment), XCD
+      // (8 g + (unit mod 8)) / G, so that an XCD's L2 holds the snapshot
+      // windows of one or two segments instead of the whole frame
+      const int G = cov_split ? fm::cov_segments(frames[i].M, frames[i].T) : 1;
+      if (cov_split) {
+        int u = 0;
+        fm::cov_each_unit(frames[i].M, prec, [&](int a, int b, int) {
+          for (int g = 0; g < G; ++g) {
+            const int x = (kXcd * g + u % kXcd) / G;
+            load[x] += (double)frames[i].T / G;
+            q[x].push_back({i, a, b, g});
+          }
+          ++u;
+        });
+      } else if (sched == 0) {
         // the whole frame onto the least-loaded XCD
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         fm::cov_each_unit(frames[i].M, prec, [&](int a, int b, int kind) {
-          load[x] += frames[i].T;
-          q[x].push_back({i, a, b, kind});
+          for (int g = 0; g < G; ++g) {
+            load[x] += (double)frames[i].T / G;
+            q[x].push_back({i, a, b, cov_split ? g : kind});
+          }
         });
       } else {
         // each unit onto the least-loaded XCD
         fm::cov_each_unit(frames[i].M, prec, [&](int a, int b, int kind) {
-          const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-          load[x] += frames[i].T;
-          q[x].push_back({i, a, b, kind});
+          for (int g = 0; g < G; ++g) {
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[x] += (double)frames[i].T / G;
+            q[x].push_back({i, a, b, cov_split ? g : kind});
+          }
         });
       }
     }
@@ -937,7 +1000,16 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
       }
     }
   }
-  add(p->cov, kCov, 0, 0, b0);
+  if (cov_split) {
+    add(p->cov, kCovSplit, 0, 0, b0);
+    b0 = begin();
+    for (int i : order)
+      if (forms_r(i))
+        fm::cov_each_unit(frames[i].M, prec, [&](int a, int b, int) { items.push_back({i, a, b, 0}); });
+    add(p->cov, kCovSplit, 1, 0, b0);
+  } else {
+    add(p->cov, kCov, 0, 0, b0);
+  }
 
   // stage 2 init: Omega -> V / Y (Method 2), gather (Method 1)
   b0 = begin();

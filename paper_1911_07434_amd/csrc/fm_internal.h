@@ -62,6 +62,9 @@ struct FrameDev {
   float2 *hgrp;
   const int *hmem;
   int hslot, hcount;
+  // FP32 covariance with its T segments on separate waves: per unit and
+  // segment the wave's (Re, Im) sums, [unit][segment][64 values][64 lanes]
+  float *cpart;
   // model-order estimate (Sec. V-D); K_hat == null: none
   int *K_hat;           // [1]
   double *order_crit;   // [n + 1] criterion values, or null
@@ -82,6 +85,7 @@ constexpr int kGramRows = 128;     // rows of the sketch per Gram partial
 constexpr int kSmallSlots = 8;     // npad^2 complex128 matrices per frame
 constexpr int kCovTile = 128;      // 16-bit covariance: tile edge (complex entries)
 constexpr int kCovBlock = 64;      // FP32 covariance: rows of a wave block (one wave per block)
+constexpr int kCovPartFloats = 64 * 64;  // FP32 covariance: one segment's sums of a wave block
 constexpr int kCovCols = 32;       // FP32 covariance: columns of a wave block
 constexpr int kSketchRows = 128;   // rows of R per sketch workgroup
 constexpr int kApplyRows = 64;     // rows per apply / gather workgroup
@@ -112,6 +116,12 @@ hipError_t launch_covariance(const FrameDev &single, const FrameDev *frames,
                              const Item *items, int n_items, fm_prec prec, hipStream_t s);
 // 16-bit operand covariance (FM_FP16 / FM_BF16, or split hi + lo with
 // FM_FP16X3 / FM_BF16X3), FP32 accumulation
+// FP32 covariance, T segments on separate waves: mode 0 writes each
+// (unit, segment)'s sums to cpart (items {frame, bi, bj, g}, or a single
+// frame's units x segments), mode 1 reduces them in order and stores R
+// (items {frame, bi, bj, 0}, or a single frame's units)
+hipError_t launch_covariance_split(const FrameDev &single, const FrameDev *frames,
+                                   const Item *items, int n_items, int mode, hipStream_t s);
 hipError_t launch_covariance16(const FrameDev &single, const FrameDev *frames,
                                const Item *items, int n_items, fm_prec prec, hipStream_t s);
 hipError_t launch_omega(const FrameDev &single, const FrameDev *frames, const Item *items,
@@ -212,6 +222,25 @@ inline int cov_units(int M, fm_prec prec) {
   const int nt = (M + e - 1) / e;
   return prec == FM_FP32 ? nt * (nt + 1) : nt * (nt - 1) / 2 + (nt + 1) / 2;
 }
+
+// The FP32 covariance sums T in cov_segments(M, T) fixed segments of whole
+// 8-snapshot chunks (the ragged tail in the last): each segment's Gauss
+// products accumulate from zero, and R = (((0 + S_0) + S_1) + ...) / T.  A
+// wave runs the segments in turn, or one wave per segment writes S_g and a
+// reduction wave adds them in the same order: the same bits either way.  The
+// count depends on the frame's shape only: enough segments for about 2048
+// waves (two per SIMD) per frame, at most 8, each at least 32 chunks.
+inline __host__ __device__ int cov_segments(int M, int T) {
+  const int nt = (M + 63) / 64;  // kCovBlock rows per block row
+  const int by_waves = 2048 / (nt * (nt + 1));
+  const int by_len = (T >> 3) / 32;
+  const int g = by_waves < by_len ? by_waves : by_len;
+  return g < 1 ? 1 : (g > 8 ? 8 : g);
+}
+// first chunk of segment g of G over nfull chunks
+inline __host__ __device__ int cov_seg_chunk(int g, int G, int nfull) { return g * nfull / G; }
+// unit index of FP32 block (bi, bj): block row bi holds units bi (bi + 1) ..
+inline __host__ __device__ int cov_unit_index(int bi, int bj) { return bi * (bi + 1) + bj; }
 
 namespace detail {
 // 16-bit units of the row tiles [lo, lo + n) of a frame in an order where

@@ -85,6 +85,31 @@ def test_covariance_gaussian(ctx, M, T):
     assert np.all(np.diag(Rg).imag == 0)
 
 
+@pytest.mark.parametrize("M,T", [(1024, 2048), (200, 1029), (97, 1536), (64, 519)])
+def test_covariance_segments_parallel_equals_sequential_bitwise(ctx, M, T):
+    # fm_covariance runs the FP32 T segments one wave each with an in-order
+    # reduction; a plan whose blocks fill the GPU runs them in turn on one
+    # wave: the same sums in the same order, so the same bits
+    say(f"cov segments M={M} T={T}")
+    fr = fmsynth.make_frame(M, T, 3, 5.0, seed=M + 3 * T)
+    X = dev(fr.X)
+    R1 = torch.empty((M, M), dtype=torch.complex64, device="cuda")
+    ctx.fm_covariance(X, R1)
+    nfr = 2048 // ((M + 63) // 64 * ((M + 63) // 64 + 1)) + 1
+    specs = [DeviceFrame(FrameSpec(M=M, T=T, K=3, n=8, L=181, theta0_deg=-90.0,
+                                   dtheta_deg=1.0), X=X,
+                         rnd=torch.from_numpy(fmsynth.make_omega(M, 8, 1))) for _ in range(nfr)]
+    plan = fm.Plan(ctx, [d.descriptor() for d in specs])
+    plan.covariance()
+    torch.cuda.synchronize()
+    a = R1.cpu().numpy()
+    for d in specs[:3]:
+        assert np.array_equal(a, d.R.cpu().numpy())
+    Ro = oracle.covariance(fr.X, threads=oracle.default_threads())
+    assert np.linalg.norm(a - Ro) / np.linalg.norm(Ro) <= 1e-6
+    plan.close()
+
+
 def test_covariance_leading_dimensions(ctx):
     M, T = 70, 90
     fr = fmsynth.make_frame(M, T, 2, 5.0, seed=3)
