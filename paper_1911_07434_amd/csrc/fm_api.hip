@@ -99,7 +99,8 @@ struct fm_plan {
 
 namespace {
 
-enum Kind { kCov, kCovSplit, kOmega, kGather, kSketch, kSketch16, kXhv, kXz, kZx, kXcore, kGram, kSmall, kApply,
+enum Kind { kCov, kCovSplit, kOmega, kGather, kSketch, kSketch16, kSketchSeg, kSketch16Seg,
+             kSketchRed, kSketch16Red, kXhv, kXz, kZx, kXcore, kGram, kSmall, kApply,
              kSpecPrep, kRefine, kPeaks, kOrder, kAcorr, kHsum, kPoly, kEsprit, kSplit16, kSpec16 };
 
 fm_status fail(fm_ctx *ctx, fm_status st, const char *fmt, ...) {
@@ -125,15 +126,29 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr long long kCovSplitWaves = 2048;
 // ... and their segment sums fit in this much workspace
 constexpr size_t kCovSplitBytes = (size_t)64 << 20;
+// ... and the Method 2 products' channel segments run on separate workgroups
+// when its row-block workgroups number fewer than this (two per CU)
+constexpr long long kSketchSplitWGs = 512;
 
 // per-frame workspace layout (shared by single-frame calls and plans)
 struct WsLayout {
-  size_t y, v, z, part, small, uf, rlist, eig, total;
-  bool has_z;
+  size_t y, v, z, part, small, uf, rlist, eig, spart, total;
+  bool has_z, has_spart;
 };
 
-// Tz > 0: Method 2 from X, with the [T][n] product X^H V
-WsLayout ws_layout(int M, int n, int K, int L, int Tz = 0) {
+int sketch_nb(int n);
+// bytes of a frame's Method 2 channel-segment sums (0 without segments)
+size_t spart_bytes(int M, int n) {
+  const int nb = sketch_nb(n), S = fm::sketch_segments(M, nb);
+  if (S <= 1) return 0;
+  return (size_t)((M + fm::kSketchRows - 1) / fm::kSketchRows) * S * nb * fm::kSketchPartFloats *
+         sizeof(float);
+}
+
+// Tz > 0: Method 2 from X, with the [T][n] product X^H V; with_spart: room
+// for the channel-segment sums (single-frame calls run their products with
+// R one workgroup per segment; plans add it only when they do)
+WsLayout ws_layout(int M, int n, int K, int L, int Tz = 0, bool with_spart = true) {
   const int np = (n + 1) & ~1;
   const int nchunk = (M + fm::kGramRows - 1) / fm::kGramRows;
   WsLayout w;
@@ -147,6 +162,9 @@ WsLayout ws_layout(int M, int n, int K, int L, int Tz = 0) {
   w.uf = o;    o += align256((size_t)M * K * 8);
   w.rlist = o; o += align256((size_t)(L + 1) * 4);
   w.eig = o;   o += align256((size_t)n * 8);
+  const size_t sp = with_spart && Tz == 0 ? spart_bytes(M, n) : 0;
+  w.has_spart = sp > 0;
+  w.spart = o; o += align256(sp);
   w.total = o;
   return w;
 }
@@ -158,6 +176,7 @@ void bind_ws(FrameDev &f, char *base, const WsLayout &w) {
   f.part = reinterpret_cast<double2 *>(base + w.part);
   f.small = reinterpret_cast<double2 *>(base + w.small);
   f.Uf = reinterpret_cast<float2 *>(base + w.uf);
+  f.spart = w.has_spart ? reinterpret_cast<float *>(base + w.spart) : nullptr;
   f.rlist = reinterpret_cast<int *>(base + w.rlist);
   f.eig = reinterpret_cast<double *>(base + w.eig);
   f.nchunk = (f.M + fm::kGramRows - 1) / fm::kGramRows;
@@ -265,8 +284,17 @@ hipError_t run_project_single(FrameDev &f, hipStream_t s, fm_prec prec) {
       hipError_t e2 = fm::launch_xhv(f, nullptr, nullptr, 0, nb, s);
       return e2 != hipSuccess ? e2 : fm::launch_xz(f, nullptr, nullptr, 0, nb, r, s);
     }
-    return s16 ? fm::launch_sketch16(f, nullptr, nullptr, 0, nb, r, s)
-               : fm::launch_sketch(f, nullptr, nullptr, 0, nb, r, s);
+    // channel segments on separate workgroups, then their in-order sum:
+    // the same bits as one workgroup running them in turn
+    auto launch = [&](int split) {
+      return s16 ? fm::launch_sketch16(f, nullptr, nullptr, 0, nb, r, split, s)
+                 : fm::launch_sketch(f, nullptr, nullptr, 0, nb, r, split, s);
+    };
+    if (fm::sketch_segments(f.M, nb) > 1 && f.spart) {
+      const hipError_t e2 = launch(1);
+      return e2 != hipSuccess ? e2 : launch(2);
+    }
+    return launch(0);
   };
   const bool fused = fm::sketch_fuses_gram(nb);
   // orth of the current Y; `after_sketch`: the Gram partials came with it
@@ -697,8 +725,12 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kCovSplit: return fm::launch_covariance_split(cls, fr, it, L.count, L.mode, s);
     case kOmega: return fm::launch_omega(cls, fr, it, L.count, 0, s);
     case kGather: return fm::launch_gather(cls, fr, it, L.count, s);
-    case kSketch: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, L.mode, s);
-    case kSketch16: return fm::launch_sketch16(cls, fr, it, L.count, L.n_class, L.mode, s);
+    case kSketch: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, L.mode, 0, s);
+    case kSketch16: return fm::launch_sketch16(cls, fr, it, L.count, L.n_class, L.mode, 0, s);
+    case kSketchSeg: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, L.mode, 1, s);
+    case kSketch16Seg: return fm::launch_sketch16(cls, fr, it, L.count, L.n_class, L.mode, 1, s);
+    case kSketchRed: return fm::launch_sketch(cls, fr, it, L.count, L.n_class, L.mode, 2, s);
+    case kSketch16Red: return fm::launch_sketch16(cls, fr, it, L.count, L.n_class, L.mode, 2, s);
     case kXhv: return fm::launch_xhv(cls, fr, it, L.count, L.n_class, s);
     case kXz: return fm::launch_xz(cls, fr, it, L.count, L.n_class, L.mode, s);
     case kZx: return fm::launch_zx(cls, fr, it, L.count, s);
@@ -793,7 +825,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     const bool fx = frames[i].method == FM_METHOD_PROJECT_X ||
                     frames[i].method == FM_METHOD_SAMPLE_X;
     lay[i] = ws_layout(frames[i].M, frames[i].n, frames[i].K, frames[i].L,
-                       fx ? frames[i].T : 0);
+                       fx ? frames[i].T : 0, false);
     off[i] = total;
     total += lay[i].total;
   }
@@ -853,6 +885,30 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     cov_split = segs && waves < kCovSplitWaves && cbytes <= kCovSplitBytes;
     if (cov_split) total += cbytes;
   }
+  // Method 2 products with R, channel segments on separate workgroups when
+  // the plan's row-block workgroups are few (same bits as in turn)
+  auto seg_r = [&](int i) {
+    return frames[i].method == FM_METHOD_PROJECT &&
+           fm::sketch_segments(frames[i].M, sketch_nb(frames[i].n)) > 1;
+  };
+  bool sk_split = false;
+  std::vector<size_t> soff(n_frames, 0);
+  {
+    long long wgs = 0;
+    size_t sbytes = 0;
+    bool any = false;
+    for (int i = 0; i < n_frames; ++i)
+      if (frames[i].method == FM_METHOD_PROJECT) {
+        wgs += (frames[i].M + fm::kSketchRows - 1) / fm::kSketchRows;
+        if (seg_r(i)) {
+          any = true;
+          soff[i] = total + sbytes;
+          sbytes += align256(spart_bytes(frames[i].M, frames[i].n));
+        }
+      }
+    sk_split = any && wgs < kSketchSplitWGs && sbytes <= kCovSplitBytes;
+    if (sk_split) total += sbytes;
+  }
   p->ws_bytes = total;
   hipError_t e = hipSuccess;
   if (dry_run) {
@@ -900,6 +956,7 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     f.or_status = 1;
     bind_ws(f, p->ws + off[i], lay[i]);
     if (cov_split && forms_r(i)) f.cpart = reinterpret_cast<float *>(p->ws + coff[i]);
+    if (sk_split && seg_r(i)) f.spart = reinterpret_cast<float *>(p->ws + soff[i]);
     if (grp_of[i] >= 0) {
       f.hgrp = reinterpret_cast<float2 *>(p->ws + goff[grp_of[i]]);
       f.hslot = slot_of[i];
@@ -1069,12 +1126,26 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   auto from_x = [&](int i) { return frames[i].method == FM_METHOD_PROJECT_X; };
   auto sketch_round = [&](auto pred, int round) {
     for (int nb = 1; nb <= 4; ++nb) {
+      const bool s16 = prec != FM_FP32 && fm::sketch16_ok(nb);
       size_t b = begin();
       for (int i : order)
-        if (pred(i) && !from_x(i) && sketch_nb(frames[i].n) == nb)
+        if (pred(i) && !from_x(i) && sketch_nb(frames[i].n) == nb) {
+          // split: one item per channel segment (Item::c); frames without
+          // segments run whole in the same launch
+          const int S = sk_split && seg_r(i) ? fm::sketch_segments(frames[i].M, nb) : 1;
           for (int c = 0; c < rows(frames[i].M, fm::kSketchRows); ++c)
-            items.push_back({i, c, 0, 0});
-      add(p->sub, (prec != FM_FP32 && fm::sketch16_ok(nb)) ? kSketch16 : kSketch, round, nb, b);
+            for (int sg = 0; sg < S; ++sg) items.push_back({i, c, 0, sg});
+        }
+      add(p->sub, sk_split ? (s16 ? kSketch16Seg : kSketchSeg) : (s16 ? kSketch16 : kSketch),
+          round, nb, b);
+      if (sk_split) {
+        b = begin();
+        for (int i : order)
+          if (pred(i) && !from_x(i) && sketch_nb(frames[i].n) == nb && seg_r(i))
+            for (int c = 0; c < rows(frames[i].M, fm::kSketchRows); ++c)
+              items.push_back({i, c, 0, 0});
+        add(p->sub, s16 ? kSketch16Red : kSketchRed, round, nb, b);
+      }
     }
     // without R: Z = X^H V for every such frame, then Y = X Z / T
     for (int nb = 1; nb <= 4; ++nb) {

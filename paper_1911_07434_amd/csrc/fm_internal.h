@@ -65,6 +65,9 @@ struct FrameDev {
   // FP32 covariance with its T segments on separate waves: per unit and
   // segment the wave's (Re, Im) sums, [unit][segment][64 values][64 lanes]
   float *cpart;
+  // Method 2 products with their channel segments on separate workgroups:
+  // [row block][segment][column block][16][256 threads]
+  float *spart;
   // model-order estimate (Sec. V-D); K_hat == null: none
   int *K_hat;           // [1]
   double *order_crit;   // [n + 1] criterion values, or null
@@ -130,16 +133,35 @@ hipError_t launch_omega(const FrameDev &single, const FrameDev *frames, const It
 // round >= 0: index of this product among the frame's q + 1; for nb <= 2 the
 // launch also writes the Gram partials of the step that follows (kGramSelf
 // if round < q, else kGramFinal), which then needs no gram launch.  round < 0:
-// sketch only.
+// sketch only.  split (channel segments, sketch_segments): 0 in turn, 1 one
+// workgroup per (row block, segment) writing spart (items {frame, block, 0,
+// segment}, or a single frame's blocks x segments), 2 the in-order reduction
+// and the epilogue (items {frame, block, 0, 0}).
 hipError_t launch_sketch(const FrameDev &single, const FrameDev *frames, const Item *items,
-                         int n_items, int nb, int round, hipStream_t s);
+                         int n_items, int nb, int round, int split, hipStream_t s);
 // whether a sketch of this column class forms its Gram partials itself
 inline bool sketch_fuses_gram(int nb) { return nb <= 2; }
 // compensated FP16 sketch (16-bit plans and calls), nb <= 2 only; forms the
 // Gram partials like launch_sketch
 hipError_t launch_sketch16(const FrameDev &single, const FrameDev *frames, const Item *items,
-                           int n_items, int nb, int round, hipStream_t s);
+                           int n_items, int nb, int round, int split, hipStream_t s);
 inline bool sketch16_ok(int nb) { return nb <= 2; }
+// Method 2 products with R sum the M channels in sketch_segments(M, nb)
+// fixed segments of whole 32-channel chunks (the ragged chunk in the last):
+// each segment's products accumulate from zero and the segment sums are
+// added in order.  A workgroup runs the segments in turn, or one workgroup
+// per segment writes its sums to spart and a reduction workgroup adds them
+// in the same order: the same bits.  The count depends on the frame's shape
+// only (at least four chunks per segment, at most 8; one for the wide
+// column classes).
+inline __host__ __device__ int sketch_segments(int M, int nb) {
+  if (nb > 2) return 1;
+  const int c = (M >> 5) / 4;
+  return c < 1 ? 1 : (c > 8 ? 8 : c);
+}
+inline __host__ __device__ int sketch_seg_chunk(int s, int S, int nfull) { return s * nfull / S; }
+// floats of one sketch workgroup's sums of one segment, per column block
+constexpr int kSketchPartFloats = 16 * 256;
 // products with R without forming it (Method 2 from X): R V = X (X^H V) / T.
 // launch_xhv: Z = X^H V (one workgroup per 128 snapshots); launch_xz:
 // Y = X Z / T, Gram partials as launch_sketch (one workgroup per 128 rows)

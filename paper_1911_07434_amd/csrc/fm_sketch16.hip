@@ -36,15 +36,21 @@ typedef FM_GLOBAL const f32x2 gf32x2;
 constexpr int kCh = 32;              // channels per chunk
 constexpr int kBRow = 2 * kCh + 8;   // halves per B column in LDS (16 bytes of padding)
 
-template <bool kBatched>
+// workgroup -> (frame, row block, channel segment); a single frame's split
+// launch is row blocks x segments
+template <int NB, bool kBatched>
 __device__ __forceinline__ const FrameDev &frame16(const FrameDev &single, const FrameDev *frames,
-                                                   const Item *items, int &blk) {
+                                                   const Item *items, int split, int &blk,
+                                                   int &seg) {
   if constexpr (kBatched) {
     const Item &it = items[blockIdx.x];
     blk = it.a;
+    seg = it.c;
     return frames[it.frame];
   } else {
-    blk = blockIdx.x;
+    const int S = split == 1 ? sketch_segments(single.M, NB) : 1;
+    blk = blockIdx.x / S;
+    seg = blockIdx.x % S;
     return single;
   }
 }
@@ -62,12 +68,12 @@ __device__ __forceinline__ void split8(const f32x4 &x0, const f32x4 &x1, float s
 
 template <int NB, bool kBatched>
 __global__ __launch_bounds__(256) void sketch16_kernel(FrameDev single, const FrameDev *frames,
-                                                       const Item *items, int round) {
+                                                       const Item *items, int round, int split) {
   constexpr int kPlane = 32 * NB * kBRow;  // halves in one plane (hi or lo) of one buffer
   __shared__ __attribute__((aligned(16))) _Float16 bsm[2 * 2 * kPlane];
   __shared__ float red[4];
-  int blk;
-  const FrameDev &f = frame16<kBatched>(single, frames, items, blk);
+  int blk, seg;
+  const FrameDev &f = frame16<NB, kBatched>(single, frames, items, split, blk, seg);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 31, h = lane >> 5;
   const int M = f.M, n = f.n;
@@ -201,44 +207,106 @@ __global__ __launch_bounds__(256) void sketch16_kernel(FrameDev single, const Fr
     }
   };
 
-  // full chunks: the prefetch of chunk c + 1 is clamped to the last full
-  // chunk (a repeat hits the cache), so every load in the loop is
-  // unconditional and the compiler's waits cover only what each step uses
+  // Channel segments (sketch_segments): each segment's MFMAs accumulate
+  // from zero and the segment sums are added in order.  split 0: the
+  // segments in turn (fold at each segment start); 1: segment `seg` only,
+  // its sums to spart; 2: no products, the sums read back in order -- the
+  // same bits as 0.  Full chunks: the prefetch of chunk c + 1 is clamped to
+  // the segment's last chunk (a repeat hits the cache), so every load in the
+  // loop is unconditional and the compiler's waits cover only what each
+  // step uses.
   const int nfull = M / kCh;
   const int vfull = kCh * n;
+  const int segs = sketch_segments(M, NB);
+  const int cb = split == 1 ? sketch_seg_chunk(seg, segs, nfull) : 0;
+  const int ce = split == 1 ? sketch_seg_chunk(seg + 1, segs, nfull) : (split == 2 ? 0 : nfull);
+  const bool last = split != 1 || seg == segs - 1;
+  floatx16 sum[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) sum[b][v] = 0.f;
+  int sg = 1, next = (split == 0 && segs > 1) ? sketch_seg_chunk(1, segs, nfull) : -1;
+  auto fold = [&]() {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        sum[b][v] += acc[b][v];
+        acc[b][v] = 0.f;
+      }
+  };
+  auto at = [&](int c) {
+    if (c == next) {
+      fold();
+      ++sg;
+      next = sg < segs ? sketch_seg_chunk(sg, segs, nfull) : -1;
+    }
+  };
   f32x4 a0[8], a1[8];
   __syncthreads();  // zero columns written before any staging
-  if (nfull > 0) {
-    load_b(0, vfull);
-    load_r_full(a0, 0);
+  if (ce > cb) {
+    load_b(cb, vfull);
+    load_r_full(a0, cb);
     store_b(0, vfull);
     __syncthreads();
-    for (int c = 0; c < nfull; c += 2) {
-      const int c1 = min(c + 1, nfull - 1);
+    for (int c = cb; c < ce; c += 2) {
+      const int c1 = min(c + 1, ce - 1);
       load_b(c1, vfull);
       load_r_full(a1, c1);
       __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
+      at(c);
       compute(a0, 0);
       store_b(1, vfull);
       __syncthreads();
-      if (c + 1 >= nfull) break;
-      const int c2 = min(c + 2, nfull - 1);
+      if (c + 1 >= ce) break;
+      const int c2 = min(c + 2, ce - 1);
       load_b(c2, vfull);
       load_r_full(a0, c2);
       __builtin_amdgcn_sched_barrier(0);
+      at(c + 1);
       compute(a1, 1);
       store_b(0, vfull);
       __syncthreads();
     }
   }
-  if (nfull * kCh < M) {
+  if (split != 2 && last && nfull * kCh < M) {
     // ragged last chunk; buffer 0 is free (every wave passed the last barrier)
     load_b(nfull, (M - nfull * kCh) * n);
     load_r_tail(a0, nfull);
     store_b(0, (M - nfull * kCh) * n);
     __syncthreads();
     compute(a0, 0);
-    __syncthreads();  // the epilogue reuses the LDS buffers
+  }
+  __syncthreads();  // the epilogue reuses the LDS buffers
+  if (segs > 1) {
+    // segment sums: this workgroup's slot [block][segment][NB][16][256]
+    FM_GLOBAL float *sp = (FM_GLOBAL float *)f.spart + (size_t)blk * segs * NB * kSketchPartFloats + tid;
+    if (split == 1) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) sp[((size_t)seg * NB * 16 + b * 16 + v) * 256] = acc[b][v];
+      return;
+    }
+    if (split == 2) {
+      for (int q = 0; q < segs; ++q) {
+        float t[NB][16];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 16; ++v)
+            t[b][v] = __builtin_nontemporal_load(sp + ((size_t)q * NB * 16 + b * 16 + v) * 256);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) sum[b][v] += t[b][v];
+      }
+    } else {
+      fold();
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = sum[b];
   }
 
   // store Y (unscaled), Re Y_c from column c, Im Y_c from column n + c
@@ -273,19 +341,22 @@ __global__ __launch_bounds__(256) void sketch16_kernel(FrameDev single, const Fr
 
 template <int NB>
 hipError_t launch16(const FrameDev &single, const FrameDev *frames, const Item *items,
-                    int n_items, int round, hipStream_t s) {
-  const dim3 g(items ? n_items : (single.M + kSketchRows - 1) / kSketchRows), b(256);
-  if (items) hipLaunchKernelGGL((sketch16_kernel<NB, true>), g, b, 0, s, single, frames, items, round);
-  else hipLaunchKernelGGL((sketch16_kernel<NB, false>), g, b, 0, s, single, frames, items, round);
+                    int n_items, int round, int split, hipStream_t s) {
+  const int S = split == 1 ? sketch_segments(single.M, NB) : 1;
+  const dim3 g(items ? n_items : S * ((single.M + kSketchRows - 1) / kSketchRows)), b(256);
+  if (items)
+    hipLaunchKernelGGL((sketch16_kernel<NB, true>), g, b, 0, s, single, frames, items, round, split);
+  else
+    hipLaunchKernelGGL((sketch16_kernel<NB, false>), g, b, 0, s, single, frames, items, round, split);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_sketch16(const FrameDev &single, const FrameDev *frames, const Item *items,
-                           int n_items, int nb, int round, hipStream_t s) {
-  return nb <= 1 ? launch16<1>(single, frames, items, n_items, round, s)
-                 : launch16<2>(single, frames, items, n_items, round, s);
+                           int n_items, int nb, int round, int split, hipStream_t s) {
+  return nb <= 1 ? launch16<1>(single, frames, items, n_items, round, split, s)
+                 : launch16<2>(single, frames, items, n_items, round, split, s);
 }
 
 }  // namespace fm

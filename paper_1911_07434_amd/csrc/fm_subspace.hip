@@ -111,11 +111,19 @@ typedef FM_GLOBAL const double2 gdouble2;
 // the products with R (A = R, B = V, kdim = M, scale 1) and, without forming
 // R, the second half of R V = X (X^H V) / T (A = X, B = Z, kdim = T,
 // scale 1/T).
+//
+// Channel segments (products with R): the contraction runs over `segs` fixed
+// segments of whole chunks (the ragged chunk in the last); each segment's
+// MFMAs accumulate from zero and the segment sums are added in order.
+// split 0: every segment in turn; 1: segment `seg` only, its sums to the
+// frame's spart; 2: no contraction, the sums of every segment read back from
+// spart in order -- the same bits as split 0.
 template <int NB, int SK>
 __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk, int gmode,
                                             const float2 *Am, long long lda, int kdim,
                                             const float2 *Bm, float scale,
-                                            float2 (*vbuf)[kSkChunkMax * kMaxL]) {
+                                            float2 (*vbuf)[kSkChunkMax * kMaxL],
+                                            int segs = 1, int split = 0, int seg = 0) {
   constexpr int kSkChunk = 2 * SK;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -187,30 +195,59 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
   };
 
   const int nfull = kdim / kSkChunk;
+  // this call's chunks [cb, ce); `next` is the start of the next segment
+  // (a fold point) in a sequential run
+  const int cb = split == 1 ? sketch_seg_chunk(seg, segs, nfull) : 0;
+  const int ce = split == 1 ? sketch_seg_chunk(seg + 1, segs, nfull) : (split == 2 ? 0 : nfull);
+  const bool last = split != 1 || seg == segs - 1;
+  floatx16 sum[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) sum[b][v] = 0.f;
+  int sg = 1, next = (split == 0 && segs > 1) ? sketch_seg_chunk(1, segs, nfull) : -1;
+  auto fold = [&]() {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        sum[b][v] += acc[b][v];
+        acc[b][v] = 0.f;
+      }
+  };
+  auto at = [&](int c) {
+    if (c == next) {
+      fold();
+      ++sg;
+      next = sg < segs ? sketch_seg_chunk(sg, segs, nfull) : -1;
+    }
+  };
   float2 a0[SK], a1[SK];
-  if (nfull > 0) {
-    load_v(0, velems);
-    load_r_full(a0, 0);
+  if (ce > cb) {
+    load_v(cb, velems);
+    load_r_full(a0, cb);
     store_v(0, velems);
     __syncthreads();
-    for (int c = 0; c < nfull; c += 2) {
+    for (int c = cb; c < ce; c += 2) {
       // chunk c from (a0, vbuf[0]); chunk c+1 from (a1, vbuf[1])
-      const int c1 = min(c + 1, nfull - 1);
+      const int c1 = min(c + 1, ce - 1);
       load_v(c1, velems);
       load_r_full(a1, c1);
+      at(c);
       compute(a0, vbuf[0]);
       store_v(1, velems);
       __syncthreads();
-      if (c + 1 >= nfull) break;
-      const int c2 = min(c + 2, nfull - 1);
+      if (c + 1 >= ce) break;
+      const int c2 = min(c + 2, ce - 1);
       load_v(c2, velems);
       load_r_full(a0, c2);
+      at(c + 1);
       compute(a1, vbuf[1]);
       store_v(0, velems);
       __syncthreads();
     }
   }
-  if (nfull * kSkChunk < kdim) {
+  if (split != 2 && last && nfull * kSkChunk < kdim) {
     // ragged last chunk: columns past kdim read as zero, V rows past kdim
     // are zero in LDS; vbuf[0] is free (every wave passed the last barrier)
     const int c = nfull;
@@ -225,6 +262,35 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
     store_v(0, lim);
     __syncthreads();
     compute(a0, vbuf[0]);
+  }
+  if (segs > 1) {
+    // segment sums: this workgroup's slot [chunk][segment][NB][16][256]
+    FM_GLOBAL float *sp = (FM_GLOBAL float *)f.spart + (size_t)chunk * segs * NB * 4096 + tid;
+    if (split == 1) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) sp[((size_t)seg * NB * 16 + b * 16 + v) * 256] = acc[b][v];
+      return;
+    }
+    if (split == 2) {
+      for (int q = 0; q < segs; ++q) {
+        float t[NB][16];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 16; ++v)
+            t[b][v] = __builtin_nontemporal_load(sp + ((size_t)q * NB * 16 + b * 16 + v) * 256);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) sum[b][v] += t[b][v];
+      }
+    } else {
+      fold();
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = sum[b];
   }
   if (scale != 1.f) {
 #pragma unroll
@@ -277,17 +343,32 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
 // `round` is the index of this product among the frame's q + 1: for column
 // classes NB <= 2 the Gram partials that follow it (orth of the next round,
 // or the final core and Gram after the last product) are formed here.
+// split: 0 every channel segment in turn, 1 one segment (Item::c, or the
+// single frame's blockIdx % segments), 2 the in-order reduction
 template <int NB, bool kBatched>
 __global__ __launch_bounds__(256) void sketch_kernel(FrameDev single, const FrameDev *frames,
-                                                     const Item *items, int round) {
+                                                     const Item *items, int round, int split) {
   __shared__ float2 vbuf[2][kSkChunkMax * kMaxL];
-  int blk, unused;
-  const FrameDev &f = frame_of<kBatched>(single, frames, items, blk, unused);
+  int blk, seg = 0;
+  const FrameDev *fp;
+  if constexpr (kBatched) {
+    const Item &it = items[blockIdx.x];
+    fp = &frames[it.frame];
+    blk = it.a;
+    seg = it.c;
+  } else {
+    fp = &single;
+    const int S = split == 1 ? sketch_segments(single.M, NB) : 1;
+    blk = blockIdx.x / S;
+    seg = blockIdx.x % S;
+  }
+  const FrameDev &f = *fp;
   // every wave takes part in the V staging and the barriers; waves whose
   // rows start past M clamp to row M-1 and store nothing
   const int i0 = blk * kSketchRows + (threadIdx.x >> 6) * 32;
   const int gmode = round < 0 ? -1 : (round < f.q ? kGramSelf : kGramFinal);
-  sketch_rows<NB, (NB <= 2 ? 16 : 8)>(f, i0, blk, gmode, f.R, f.ldr, f.M, f.V, 1.f, vbuf);
+  sketch_rows<NB, (NB <= 2 ? 16 : 8)>(f, i0, blk, gmode, f.R, f.ldr, f.M, f.V, 1.f, vbuf,
+                                      sketch_segments(f.M, NB), split, seg);
 }
 
 // ---------------------------------------------------------------------------
@@ -1452,12 +1533,13 @@ hipError_t launch_omega(const FrameDev &single, const FrameDev *frames, const It
 }
 
 hipError_t launch_sketch(const FrameDev &single, const FrameDev *frames, const Item *items,
-                         int n_items, int nb, int round, hipStream_t s) {
-  const dim3 g(items ? n_items : (single.M + kSketchRows - 1) / kSketchRows), b(256);
+                         int n_items, int nb, int round, int split, hipStream_t s) {
+  const int S = split == 1 ? sketch_segments(single.M, nb) : 1;
+  const dim3 g(items ? n_items : S * ((single.M + kSketchRows - 1) / kSketchRows)), b(256);
   const int rd = nb <= 2 ? round : -1;
-#define FM_SK(NB)                                                                                 \
-  if (items) hipLaunchKernelGGL((sketch_kernel<NB, true>), g, b, 0, s, single, frames, items, rd); \
-  else hipLaunchKernelGGL((sketch_kernel<NB, false>), g, b, 0, s, single, frames, items, rd);
+#define FM_SK(NB)                                                                                        \
+  if (items) hipLaunchKernelGGL((sketch_kernel<NB, true>), g, b, 0, s, single, frames, items, rd, split); \
+  else hipLaunchKernelGGL((sketch_kernel<NB, false>), g, b, 0, s, single, frames, items, rd, split);
   switch (nb) {
     case 1: FM_SK(1); break;
     case 2: FM_SK(2); break;

@@ -110,6 +110,36 @@ def test_covariance_segments_parallel_equals_sequential_bitwise(ctx, M, T):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("M,n", [(1024, 16), (300, 24)])
+def test_sketch_segments_parallel_equals_sequential_bitwise(ctx, prec, M, n):
+    # single-frame Method 2 runs each product's channel segments on separate
+    # workgroups with an in-order reduction; a plan with enough row blocks
+    # runs them in turn in one workgroup: the same bits
+    say(f"sketch segments M={M} n={n} {prec}")
+    p = {"fp32": fm.FM_FP32, "fp16": fm.FM_FP16}[prec]
+    T, K, q = 2 * M, 4, 2
+    fr = fmsynth.make_frame(M, T, K, 5.0, seed=M + n)
+    X = dev(fr.X)
+    Om = torch.from_numpy(fmsynth.make_omega(M, n, 5))
+    alone = DeviceFrame(FrameSpec(M=M, T=T, K=K, n=n, q=q, L=181, theta0_deg=-90.0,
+                                  dtheta_deg=1.0), X=X, rnd=Om)
+    run_single(ctx, alone, prec=p)
+    nfr = 512 // ((M + 127) // 128) + 1
+    devs = [DeviceFrame(FrameSpec(M=M, T=T, K=K, n=n, q=q, L=181, theta0_deg=-90.0,
+                                  dtheta_deg=1.0), X=X, rnd=Om) for _ in range(nfr)]
+    plan = fm.Plan(ctx, [d.descriptor() for d in devs], prec=p)
+    plan.run()
+    torch.cuda.synchronize()
+    a = alone.results()
+    for d in devs[:2]:
+        b = d.results()
+        assert np.array_equal(a["Us"], b["Us"])
+        assert np.array_equal(a["sigma"], b["sigma"])
+        assert np.array_equal(a["P"], b["P"])
+    plan.close()
+
+
 def test_covariance_leading_dimensions(ctx):
     M, T = 70, 90
     fr = fmsynth.make_frame(M, T, 2, 5.0, seed=3)
