@@ -129,6 +129,9 @@ constexpr size_t kCovSplitBytes = (size_t)64 << 20;
 // ... and the Method 2 products' channel segments run on separate workgroups
 // when its row-block workgroups number fewer than this (two per CU)
 constexpr long long kSketchSplitWGs = 512;
+// ... and the lag sums take one lag per lane when their workgroups would
+// number fewer than this
+constexpr long long kAcorrWideWGs = 512;
 
 // per-frame workspace layout (shared by single-frame calls and plans)
 struct WsLayout {
@@ -679,7 +682,7 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
     f.hslot = 0;
     f.hcount = 1;
     FM_CHECK_LAUNCH(ctx, fm::launch_uf(f, s));
-    FM_CHECK_LAUNCH(ctx, fm::launch_acorr(f, nullptr, nullptr, 0, s));
+    FM_CHECK_LAUNCH(ctx, fm::launch_acorr(f, nullptr, nullptr, 0, 1, s));
     if (fm::acorr_blocks(M) > 1) FM_CHECK_LAUNCH(ctx, fm::launch_hsum(f, nullptr, nullptr, 0, s));
     FM_CHECK_LAUNCH(ctx, fm::launch_poly(f, nullptr, nullptr, 0, nnb, s));
   } else {
@@ -742,7 +745,7 @@ hipError_t run_launch(fm_plan *p, const fm_plan::Launch &L, hipStream_t s) {
     case kRefine: return fm::launch_refine(cls, fr, it, L.count, s);
     case kPeaks: return fm::launch_peaks(cls, fr, it, L.count, s);
     case kOrder: return fm::launch_order(cls, fr, it, L.count, s);
-    case kAcorr: return fm::launch_acorr(cls, fr, it, L.count, s);
+    case kAcorr: return fm::launch_acorr(cls, fr, it, L.count, L.mode, s);
     case kHsum: return fm::launch_hsum(cls, fr, it, L.count, s);
     case kPoly: return fm::launch_poly(cls, fr, it, L.count, L.mode, s);
     case kEsprit: return fm::launch_esprit(cls, fr, it, L.count, s);
@@ -1208,12 +1211,18 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
   b0 = begin();
   for (int i : order) items.push_back({i, 0, 0, 0});
   add(p->spec, kSpecPrep, 0, 0, b0);
+  // one lag per lane (four times the workgroups, the same bits) when the
+  // plan's lag-sum workgroups would be few
+  long long acw = 0;
+  for (int i : order)
+    if (grp_of[i] >= 0) acw += (long long)rows(frames[i].M, fm::kAcorrLags) * fm::acorr_blocks(frames[i].M);
+  const int ac_wide = acw < kAcorrWideWGs ? 1 : 0;
   b0 = begin();
   for (int i : order)
     if (grp_of[i] >= 0)
-      for (int c = 0; c < rows(frames[i].M, fm::kAcorrLags); ++c)
+      for (int c = 0; c < rows(frames[i].M, fm::acorr_lags(ac_wide)); ++c)
         for (int b = 0; b < fm::acorr_blocks(frames[i].M); ++b) items.push_back({i, c, b, 0});
-  add(p->spec, kAcorr, 0, 0, b0);
+  add(p->spec, kAcorr, ac_wide, 0, b0);
   b0 = begin();
   for (const auto &g : groups)
     if (fm::acorr_blocks(frames[g[0]].M) > 1)

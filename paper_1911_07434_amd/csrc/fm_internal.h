@@ -216,8 +216,11 @@ hipError_t launch_spectrum16(const FrameDev &single, const FrameDev *frames, con
 // (hsum_chunks(M) workgroups per group), launch_poly evaluates a group of up
 // to 16 frames over tiles of 64 nnb angles (nnb in {1, 2, 4}); the items of
 // the last two name the group's first frame
+// wide: one lag per lane, 64 lags per workgroup (four times the
+// workgroups, the same bits), for single frames and small plans
 hipError_t launch_acorr(const FrameDev &single, const FrameDev *frames, const Item *items,
-                        int n_items, hipStream_t s);
+                        int n_items, int wide, hipStream_t s);
+inline int acorr_lags(int wide) { return wide ? 64 : kAcorrLags; }
 int hsum_chunks(int M);
 hipError_t launch_hsum(const FrameDev &single, const FrameDev *frames, const Item *items,
                        int n_items, hipStream_t s);

@@ -35,13 +35,15 @@ using namespace steer;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kAcL = 4;                        // adjacent lags per lane
-constexpr int kAcLanes = kAcorrLags / kAcL;    // lanes per lag chunk (one wave)
+// kAcL adjacent lags per lane (4; 1 for single frames and small plans,
+// acorr_wide): a wave covers 64 kAcL lags, the workgroup's lag chunk.  A
+// lag's sums run in the same order either way (k outer, m ascending within
+// a half block, then the halves), so both forms give the same bits.
+constexpr int kAcLanes = 64;                   // lanes per lag chunk (one wave)
 constexpr int kAcWaves = 2;                    // waves per row block
 constexpr int kAcThreads = kAcLanes * kAcWaves;
 constexpr int kAcSub = kAcorrRows / kAcWaves;  // rows per wave
-static_assert(kAcLanes == 64, "one wave covers a lag chunk");
-constexpr int kPadShift = kAcL == 4 ? 3 : 4;   // lag-window padding period 8 (16 for 8 lags)
+static_assert(kAcorrLags == 4 * kAcLanes, "the 4-lag form covers kAcorrLags");
 
 // One workgroup (two waves): kAcorrLags consecutive lags d0.. of one frame,
 // kAcL adjacent lags per lane, over one block of kAcorrRows rows m, each
@@ -53,15 +55,17 @@ constexpr int kPadShift = kAcL == 4 ? 3 : 4;   // lag-window padding period 8 (1
 // of a lane's later lags add exact zeros.  Summation order within a half
 // block: k outer, m ascending; the blocks are added in order by the
 // polynomial pass.
-template <bool kBatched>
+template <int kAcL, bool kBatched>
 __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
                                                            const FrameDev *frames,
                                                            const Item *items) {
+  constexpr int kLags = kAcLanes * kAcL;           // lags per workgroup
+  constexpr int kPadShift = kAcL == 4 ? 3 : 4;     // lag-window padding period
   __shared__ float2 wa[kAcorrRows];
   // the lag window, one float2 of padding after every 2^kPadShift: lane l
   // reads element kAcL l + c, and without the padding lanes 64 / kAcL apart
   // would hit the same LDS banks (with it, at most two lanes share a bank)
-  constexpr int kWbN = kAcorrRows + kAcorrLags + kAcL;
+  constexpr int kWbN = kAcorrRows + kLags + kAcL;
   __shared__ float2 wb[kWbN + (kWbN >> kPadShift) + 1];
   __shared__ float2 part[kAcL][kAcLanes];  // second wave's sums
   int chunk, rb;
@@ -82,7 +86,7 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
   const int slot = fp->hslot;
   const int tid = threadIdx.x;
   const int lane = tid & (kAcLanes - 1), wave = tid / kAcLanes;
-  const int d0 = chunk * kAcorrLags;
+  const int d0 = chunk * kLags;
   const int dl = d0 + kAcL * lane;          // this lane's first lag
   const int m0 = rb * kAcorrRows;
   const int mw = m0 + wave * kAcSub;        // this wave's first row
@@ -336,15 +340,23 @@ hipError_t launch_poly_nnb(const FrameDev &single, const FrameDev *frames, const
 }  // namespace
 
 hipError_t launch_acorr(const FrameDev &single, const FrameDev *frames, const Item *items,
-                        int n_items, hipStream_t s) {
+                        int n_items, int wide, hipStream_t s) {
   if (items) {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(acorr_kernel<true>, dim3(n_items), dim3(kAcThreads), 0, s, single, frames,
-                       items);
+    if (wide)
+      hipLaunchKernelGGL((acorr_kernel<1, true>), dim3(n_items), dim3(kAcThreads), 0, s, single,
+                         frames, items);
+    else
+      hipLaunchKernelGGL((acorr_kernel<4, true>), dim3(n_items), dim3(kAcThreads), 0, s, single,
+                         frames, items);
   } else {
-    const int chunks = (single.M + kAcorrLags - 1) / kAcorrLags;
-    hipLaunchKernelGGL(acorr_kernel<false>, dim3(chunks, acorr_blocks(single.M)), dim3(kAcThreads),
-                       0, s, single, frames, items);
+    const int chunks = (single.M + acorr_lags(wide) - 1) / acorr_lags(wide);
+    if (wide)
+      hipLaunchKernelGGL((acorr_kernel<1, false>), dim3(chunks, acorr_blocks(single.M)),
+                         dim3(kAcThreads), 0, s, single, frames, items);
+    else
+      hipLaunchKernelGGL((acorr_kernel<4, false>), dim3(chunks, acorr_blocks(single.M)),
+                         dim3(kAcThreads), 0, s, single, frames, items);
   }
   return hipGetLastError();
 }
