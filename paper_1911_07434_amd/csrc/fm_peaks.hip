@@ -62,10 +62,23 @@ __global__ __launch_bounds__(kPeakThreads) void peaks_kernel(FrameDev single,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // thread tid owns l = tid, tid + 1024, ... (coalesced across the wave)
   const int per = (L + kPeakThreads - 1) / kPeakThreads;
+  // up to kKeep scan positions per thread (L <= 32768) keep their flags in a
+  // bit mask for the compaction below, which then reloads only the peaks;
+  // the loads of eight positions are issued before their tests
+  constexpr int kKeep = 32;
+  unsigned keep = 0;
   int mine = 0;
-  for (int j = 0; j < per; ++j) {
-    float v;
-    mine += is_peak(P, L, tid + j * kPeakThreads, v);
+  for (int j0 = 0; j0 < per; j0 += 8) {
+    float v[8];
+    bool pk[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) pk[u] = is_peak(P, L, tid + (j0 + u) * kPeakThreads, v[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (j0 + u < per && pk[u]) {
+        ++mine;
+        if (j0 + u < kKeep) keep |= 1u << (j0 + u);
+      }
   }
   // exclusive scan of the per-thread counts: wave scan, then wave offsets
   int incl = mine;
@@ -93,10 +106,17 @@ __global__ __launch_bounds__(kPeakThreads) void peaks_kernel(FrameDev single,
   const bool in_lds = total <= kPeakCap;
   if (in_lds) {
     int pos = wcount[wave] + incl - mine;
-    for (int j = 0; j < per; ++j) {
-      const int l = tid + j * kPeakThreads;
-      float v;
-      if (is_peak(P, L, l, v)) list[pos++] = Cand{v, l};
+    if (per <= kKeep) {
+      for (unsigned m = keep; m; m &= m - 1) {
+        const int l = tid + __builtin_ctz(m) * kPeakThreads;
+        list[pos++] = Cand{P[l], l};
+      }
+    } else {
+      for (int j = 0; j < per; ++j) {
+        const int l = tid + j * kPeakThreads;
+        float v;
+        if (is_peak(P, L, l, v)) list[pos++] = Cand{v, l};
+      }
     }
   }
   __syncthreads();
