@@ -770,21 +770,36 @@ def main():
         log(f"plain MUSIC (rocSOLVER eigh): {vplain:.2f} frames/s")
 
         # ---- one frame alone: latency distribution -------------------------
-        lat = []
-        single = frames2[:1]
-        plan_one = fm.Plan(ctx, [single[0].descriptor()])
-        with torch.cuda.stream(stream):
-            for i in range(3):
-                step(plan_one)
-            torch.cuda.synchronize()
-            for i in range(40):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                step(plan_one)
-                e1.record(stream)
-                e1.synchronize()
-                lat.append(e0.elapsed_time(e1))
-        del plan_one
+        # (stage by stage with events between the stages, and the whole frame
+        # as one graph replay; FP32 path, then the mixed path)
+        def alone(prec):
+            lat, lat_g, st = [], [], []
+            plan_one = fm.Plan(ctx, [frames2[0].descriptor()], prec=prec)
+            with torch.cuda.stream(stream):
+                for i in range(3):
+                    step(plan_one)
+                    plan_one.run(use_graph=True, stream=stream)
+                torch.cuda.synchronize()
+                for i in range(40):
+                    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+                    step(plan_one, ev)
+                    ev[4].synchronize()
+                    lat.append(ev[0].elapsed_time(ev[4]))
+                    st.append([ev[j].elapsed_time(ev[j + 1]) for j in range(4)])
+                for i in range(40):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    plan_one.run(use_graph=True, stream=stream)
+                    e1.record(stream)
+                    e1.synchronize()
+                    lat_g.append(e0.elapsed_time(e1))
+            del plan_one
+            return {"p50": round(float(np.percentile(lat, 50)), 3),
+                    "p99": round(float(np.percentile(lat, 99)), 3),
+                    "stage_ms_p50": {n: round(float(np.median([x[j] for x in st])), 4)
+                                     for j, n in enumerate(stage_names)},
+                    "graph_replay_p50": round(float(np.percentile(lat_g, 50)), 3),
+                    "graph_replay_p99": round(float(np.percentile(lat_g, 99)), 3)}
         out["comparison"] = {
             "method1_frames_per_s": round(v1, 2),
             "plain_music_frames_per_s": round(vplain, 3),
@@ -792,8 +807,9 @@ def main():
             "speedup_method2_vs_plain": round(value / vplain, 1),
             "speedup_method1_vs_plain": round(v1 / vplain, 1),
         }
-        out["frame_latency_ms_alone"] = {"p50": round(float(np.percentile(lat, 50)), 3),
-                                         "p99": round(float(np.percentile(lat, 99)), 3)}
+        out["frame_latency_ms_alone"] = alone(fm.FM_FP32)
+        out["frame_latency_ms_alone"]["fp16"] = alone(fm.FM_FP16)
+        log(f"one frame alone: {out['frame_latency_ms_alone']}")
 
     # ---- large frames (M = 4096, T = 8192) at every precision -------------
     if "large" in legs:

@@ -428,11 +428,13 @@ class GpuExecutor:
                         torch.sin(th * (np.pi / 180.0)))
         x = x - 2.0 * torch.floor(x * 0.5)
         A = torch.polar(torch.ones_like(x), -np.pi * x).to(torch.complex64)
-        z = torch.randn((2, M + K, T), generator=self.gen, device=dev)
-        S = torch.complex(z[0, M:], z[1, M:]) * np.float32(np.sqrt(0.5))
-        torch.matmul(A, S, out=out)
-        sig = np.float32(np.sqrt(10.0 ** (-req.snr_db / 10.0) / 2.0))
-        out.add_(torch.complex(z[0, :M], z[1, :M]), alpha=sig)
+        # circularly symmetric complex Gaussians (real and imaginary parts of
+        # variance 1/2): unit-power sources S, noise N of power sigma^2; the
+        # snapshots X = A S + sigma N: N drawn into X, then one GEMM on it
+        S = torch.randn((K, T), generator=self.gen, device=dev, dtype=torch.complex64)
+        torch.randn((M, T), generator=self.gen, out=out)
+        sig = float(np.float32(np.sqrt(10.0 ** (-req.snr_db / 10.0))))
+        out.addmm_(A, S, beta=sig)
 
     def _omega(self, M, l):
         key = (M, l)
