@@ -94,8 +94,8 @@ def serve_legs(ctx, fm, torch, seconds, seed):
     path four: more concurrent, smaller batches cut p50 and p99 at the same
     sustained rate) with HBM-budget admission
     (the budget counts snapshots, covariance, outputs and plans).  The mixed
-    path runs again with a budget of twice its mean in-flight bytes, which
-    binds: admission waits are reported.  Standard MUSIC (rocSOLVER
+    path runs again with a budget of four times its mean in-flight bytes,
+    which binds: admission waits are reported.  Standard MUSIC (rocSOLVER
     eigen-decomposition per frame) is run on the head of the same arrival
     trace."""
     from paper_1911_07434_amd.serve import GpuExecutor, Server, WallClock, poisson_arrivals
@@ -124,7 +124,7 @@ def serve_legs(ctx, fm, torch, seconds, seed):
         del ex
         torch.cuda.empty_cache()
     # the mixed path again, with a budget that binds
-    bound = int(2 * res["fp16"]["mean_inflight_bytes"]) // 256 * 256
+    bound = int(4 * res["fp16"]["mean_inflight_bytes"]) // 256 * 256
     reqs = poisson_arrivals(2000.0, seconds, seed=seed + 1)
     ex = GpuExecutor(ctx, pool_bytes=bound, n_streams=streams["fp16"], prec=fm.FM_FP16)
     clock = WallClock()
