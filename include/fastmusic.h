@@ -458,7 +458,9 @@ fm_status fm_plan_run(fm_plan *plan, void *stream, int use_graph);
  *   FM_KNOB_SPEC_ANGLES    bucket = ceil(K/8) - 1 (0..7).  Angles per
  *                          workgroup of the FP32 (polynomial) spectrum pass
  *                          of a group of frames of that bucket: 64, 128, or
- *                          256 (buckets 0..3 only).
+ *                          256 (buckets 0..3 only).  A plan (or call) whose
+ *                          pass would then have fewer than 256 workgroups
+ *                          takes 64 angles per workgroup instead.
  *   FM_KNOB_SPEC16_ANGLES  the same for the compensated FP16 spectrum pass. */
 typedef enum {
   FM_KNOB_COV_SCHEDULE = 0,

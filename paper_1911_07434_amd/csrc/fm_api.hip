@@ -132,6 +132,10 @@ constexpr long long kSketchSplitWGs = 512;
 // ... and the lag sums take one lag per lane when their workgroups would
 // number fewer than this
 constexpr long long kAcorrWideWGs = 512;
+// ... and the polynomial pass takes 64-angle tiles, whatever the knob, when
+// the knob's tiles would number fewer than the compute units (same results:
+// a tile's angles do not depend on its width)
+constexpr long long kPolyNarrowWGs = 256;
 
 // per-frame workspace layout (shared by single-frame calls and plans)
 struct WsLayout {
@@ -677,7 +681,8 @@ FM_API fm_status fm_pseudospectrum(fm_ctx *ctx, void *stream, const void *Us, in
   const int nb = spec_nb(K);
   if (prec == FM_FP32) {
     // a group of one: lag sums, then the polynomial pass
-    const int nnb = ctx->knob[FM_KNOB_SPEC_ANGLES][nb - 1] / 64;
+    int nnb = ctx->knob[FM_KNOB_SPEC_ANGLES][nb - 1] / 64;
+    if ((L + 64 * nnb - 1) / (64 * nnb) < kPolyNarrowWGs) nnb = 1;
     f.hgrp = reinterpret_cast<float2 *>(ctx->arena + uf_bytes + rl_bytes);
     f.hslot = 0;
     f.hcount = 1;
@@ -1228,11 +1233,16 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     if (fm::acorr_blocks(frames[g[0]].M) > 1)
       for (int c = 0; c < fm::hsum_chunks(frames[g[0]].M); ++c) items.push_back({g[0], c, 0, 0});
   add(p->spec, kHsum, 0, 0, b0);
+  long long ptiles = 0;
+  for (const auto &g : groups)
+    ptiles += rows(frames[g[0]].L, ctx->knob[FM_KNOB_SPEC_ANGLES][spec_nb(frames[g[0]].K) - 1]);
+  const bool narrow = ptiles < kPolyNarrowWGs;
   for (int per : {256, 128, 64}) {
     b0 = begin();
     for (const auto &g : groups) {
       const int lead = g[0];
-      if (ctx->knob[FM_KNOB_SPEC_ANGLES][spec_nb(frames[lead].K) - 1] != per) continue;
+      const int gper = narrow ? 64 : ctx->knob[FM_KNOB_SPEC_ANGLES][spec_nb(frames[lead].K) - 1];
+      if (gper != per) continue;
       for (int t = 0; t < rows(frames[lead].L, per); ++t) items.push_back({lead, t, 0, 0});
     }
     add(p->spec, kPoly, per / 64, 0, b0);

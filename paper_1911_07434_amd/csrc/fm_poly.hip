@@ -12,10 +12,10 @@
 //
 // acorr: the lag sums h'_d of one frame in FP32 from U_s rounded to FP32, as
 //   partial sums over blocks of 256 rows (four adjacent lags per lane with a
-//   sliding register window, a two-wave workgroup per 256 lags and row
-//   block, each wave over 128 of its rows, so no lane runs longer than
-//   4 x 128 K products; the columns staged through LDS; fixed order over k,
-//   then m, then the two halves).
+//   sliding register window, a four-wave workgroup per 256 lags and row
+//   block, each wave over 64 of its rows, so no lane runs longer than
+//   4 x 64 K products; the columns staged through LDS; fixed order over k,
+//   then m, then the four quarters).
 // hsum:  adds each group's row-block partials in block order, once, into the
 //   first block, which the polynomial pass then reads.
 // poly:  frames with the same M and angle grid form groups of up to 16; the
@@ -38,21 +38,23 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // kAcL adjacent lags per lane (4; 1 for single frames and small plans,
 // acorr_wide): a wave covers 64 kAcL lags, the workgroup's lag chunk.  A
 // lag's sums run in the same order either way (k outer, m ascending within
-// a half block, then the halves), so both forms give the same bits.
+// a quarter block, then the quarters in order), so both forms give the same
+// bits.
 constexpr int kAcLanes = 64;                   // lanes per lag chunk (one wave)
-constexpr int kAcWaves = 2;                    // waves per row block
+constexpr int kAcWaves = 4;                    // waves per row block
 constexpr int kAcThreads = kAcLanes * kAcWaves;
 constexpr int kAcSub = kAcorrRows / kAcWaves;  // rows per wave
 static_assert(kAcorrLags == 4 * kAcLanes, "the 4-lag form covers kAcorrLags");
 
-// One workgroup (two waves): kAcorrLags consecutive lags d0.. of one frame,
+// One workgroup (four waves): 64 kAcL consecutive lags d0.. of one frame,
 // kAcL adjacent lags per lane, over one block of kAcorrRows rows m, each
-// wave taking half the block's rows; the block's partial sums (the first
-// half's plus the second's) go to block `rb` of the group buffer.  A lane
-// keeps the kAcL values U[k][m + d] of its lags in registers and slides them
-// by one row per step (one new LDS value per kAcL products).  A lag's rows
-// run to M - 1 - d: the staged window is zero past M, so the extra products
-// of a lane's later lags add exact zeros.  Summation order within a half
+// wave taking a quarter of the block's rows; the block's partial sums (the
+// quarters' sums added in order) go to block `rb` of the group buffer.  A
+// lane keeps the kAcL values U[k][m + d] of its lags in registers and slides
+// them by one row per step (one new LDS value per kAcL products), reading
+// the LDS values of eight steps ahead of their use.  A lag's rows run to
+// M - 1 - d: the staged window is zero past M, so the extra products of a
+// lane's later lags add exact zeros.  Summation order within a quarter
 // block: k outer, m ascending; the blocks are added in order by the
 // polynomial pass.
 template <int kAcL, bool kBatched>
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
   // would hit the same LDS banks (with it, at most two lanes share a bank)
   constexpr int kWbN = kAcorrRows + kLags + kAcL;
   __shared__ float2 wb[kWbN + (kWbN >> kPadShift) + 1];
-  __shared__ float2 part[kAcL][kAcLanes];  // second wave's sums
+  __shared__ float2 part[kAcWaves - 1][kAcL][kAcLanes];  // the other waves' sums
   int chunk, rb;
   const FrameDev *fp;
   if constexpr (kBatched) {
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
   const FM_GLOBAL double2 *Ug = (const FM_GLOBAL double2 *)Us;
   double2 pa[kWa], pb[kWb];
   auto fetch = [&](int k) {
-    const FM_GLOBAL double2 *u = Ug + (size_t)k * M;
+    const FM_GLOBAL double2 *u = Ug + (size_t)min(k, K - 1) * M;
 #pragma unroll
     for (int i = 0; i < kWa; ++i) pa[i] = u[min(m0 + tid + kAcThreads * i, M - 1)];
 #pragma unroll
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
   };
   if (m0 + d0 < M) {  // uniform: some lag of this workgroup reaches the block
     fetch(0);
-    // rows of this wave's half used by the lane's first (longest) lag
+    // rows of this wave's quarter used by the lane's first (longest) lag
     const int cnt = min(kAcSub, M - dl - mw);
     const int base = kAcL * lane + wave * kAcSub;
     const float2 *wah = wa + wave * kAcSub;
@@ -131,41 +133,57 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
       __syncthreads();  // the previous column has been read
       stage();
       __syncthreads();
-      fetch(min(k + 1, K - 1));
+      fetch(k + 1);
       if (cnt > 0) {
         float2 x[kAcL];
 #pragma unroll
         for (int j = 0; j < kAcL; ++j) x[j] = wb[base + j + ((base + j) >> kPadShift)];
-#pragma unroll 4
-        for (int i = 0; i < cnt; ++i) {
-          const float2 y = wah[i];
+        // one step: conj(U[k][m + d]) * U[k][m], m = mw + i, d = dl + j,
+        // then the window slides by the next value xn
+        auto step = [&](float2 y, float2 xn) {
 #pragma unroll
           for (int j = 0; j < kAcL; ++j) {
-            // conj(U[k][m + d]) * U[k][m], m = mw + i, d = dl + j
             re[j] = fmaf(x[j].x, y.x, fmaf(x[j].y, y.y, re[j]));
             im[j] = fmaf(x[j].x, y.y, fmaf(-x[j].y, y.x, im[j]));
           }
 #pragma unroll
           for (int j = 0; j + 1 < kAcL; ++j) x[j] = x[j + 1];
+          x[kAcL - 1] = xn;
+        };
+        int i = 0;
+        for (; i + 8 <= cnt; i += 8) {
+          float2 y[8], xn[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            y[u] = wah[i + u];
+            const int e = base + i + u + kAcL;
+            xn[u] = wb[e + (e >> kPadShift)];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) step(y[u], xn[u]);
+        }
+        for (; i < cnt; ++i) {
           const int e = base + i + kAcL;
-          x[kAcL - 1] = wb[e + (e >> kPadShift)];
+          step(wah[i], wb[e + (e >> kPadShift)]);
         }
       }
     }
   }
-  // the block's sums: first half + second half
-  if (wave == 1) {
+  // the block's sums: the quarters added in order
+  if (wave > 0) {
 #pragma unroll
-    for (int j = 0; j < kAcL; ++j) part[j][lane] = make_float2(re[j], im[j]);
+    for (int j = 0; j < kAcL; ++j) part[wave - 1][j][lane] = make_float2(re[j], im[j]);
   }
   __syncthreads();
   if (wave != 0) return;
 #pragma unroll
-  for (int j = 0; j < kAcL; ++j) {
-    const float2 o = part[j][lane];
-    re[j] += o.x;
-    im[j] += o.y;
-  }
+  for (int w = 0; w < kAcWaves - 1; ++w)
+#pragma unroll
+    for (int j = 0; j < kAcL; ++j) {
+      const float2 o = part[w][j][lane];
+      re[j] += o.x;
+      im[j] += o.y;
+    }
 #pragma unroll
   for (int j = 0; j < kAcL; ++j) {
     const int d = dl + j;

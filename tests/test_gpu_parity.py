@@ -245,11 +245,13 @@ def test_spectrum_refine_ragged(ctx, M, K, prec):
 # stage 4: peaks on identical float32 spectra (bit-exact)
 # ----------------------------------------------------------------------------
 
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("case", range(10))
 def test_peaks_bitexact(ctx, case):
+    # lengths on both sides of the scan's forms: positions held in registers
+    # (L <= 24576), flags in a bit mask (L <= 32768), full rescan beyond
     rng = np.random.default_rng(case)
-    L = [1, 2, 5, 1000, 18001, 40000][case]
-    K = [1, 2, 3, 8, 40, 64][case]
+    L = [1, 2, 5, 1000, 18001, 40000, 1025, 24576, 24577, 30000][case]
+    K = [1, 2, 3, 8, 40, 64, 5, 16, 16, 33][case]
     P = rng.integers(0, 6, size=L).astype(np.float32)      # many ties and plateaus
     if case >= 3:
         P = np.round(rng.random(L) * 50).astype(np.float32)
