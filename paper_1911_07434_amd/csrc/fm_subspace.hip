@@ -882,7 +882,8 @@ __device__ inline RotW make_rot(double ap, double aq, double2 b) {
       double t;
       if (az < 1e18) {
         const float zf = (float)az;
-        const float t0 = __builtin_amdgcn_rcpf(zf + __builtin_sqrtf(fmaf(zf, zf, 1.0f)));
+        // (hardware square root and reciprocal: a seed, refined below)
+        const float t0 = __builtin_amdgcn_rcpf(zf + __builtin_amdgcn_sqrtf(fmaf(zf, zf, 1.0f)));
         double u = (double)t0;
         const double f = fma(u, u + 2.0 * az, -1.0);
         u = fma(-f, (double)__builtin_amdgcn_rcpf((float)(2.0 * (u + az))), u);
@@ -909,9 +910,10 @@ __device__ inline RotW make_rot(double ap, double aq, double2 b) {
 // padding stays zero and the leading block's result is unchanged).  Lane l
 // owns the 2x2 block (ki, kj) = (l / 8, l % 8) of the round's pairs and
 // rows ki, ki + 8 of V's columns of pair kj.  It forms the rotation of pair
-// kj from the round's A and takes that of pair ki from lane ki (whose kj is
-// ki) by a cross-lane read, so a round needs no rotation table and no
-// workgroup barrier.  The wave's LDS reads and writes are performed in
+// kj from the round's A and takes c, s and e of pair ki from lane ki (whose
+// kj is ki) by cross-lane reads (a diagonal block, ki = kj, has its own
+// rotation already), so a round needs no rotation table and no workgroup
+// barrier.  The wave's LDS reads and writes are performed in
 // program order; the wavefront-scope fences keep the compiler from moving
 // them across the read / write split.  Call from all 64 lanes of one wave.
 __device__ __forceinline__ int rr16(int pos, int round) {
@@ -967,9 +969,6 @@ __device__ __forceinline__ int jacobi_wave16(double2 *A, double2 *V) {
       Ri.s = __shfl(Rj.s, ki);
       Ri.ex = __shfl(Rj.ex, ki);
       Ri.ey = __shfl(Rj.ey, ki);
-      Ri.ap = __shfl(Rj.ap, ki);
-      Ri.aq = __shfl(Rj.aq, ki);
-      Ri.mode = __shfl(Rj.mode, ki);
       // J = [[c, s], [-s e, c e]]: qp = -s e, qq = c e of pair kj
       const double qpx = -Rj.s * Rj.ex, qpy = -Rj.s * Rj.ey;
       const double qqx = Rj.c * Rj.ex, qqy = Rj.c * Rj.ey;
@@ -991,11 +990,12 @@ __device__ __forceinline__ int jacobi_wave16(double2 *A, double2 *V) {
       double2 d01 = make_double2(fma(Ri.c, c01.x, -Ri.s * w1.x), fma(Ri.c, c01.y, -Ri.s * w1.y));
       double2 d10 = make_double2(fma(Ri.s, c00.x, Ri.c * w0.x), fma(Ri.s, c00.y, Ri.c * w0.y));
       double2 d11 = make_double2(fma(Ri.s, c01.x, Ri.c * w1.x), fma(Ri.s, c01.y, Ri.c * w1.y));
-      if (ki == kj && Ri.mode != 0) {
-        // the pair's own 2x2 block: the rotated diagonal, A_pq annihilated
-        if (Ri.mode == 1) {
-          d00 = make_double2(Ri.ap, 0.0);
-          d11 = make_double2(Ri.aq, 0.0);
+      if (ki == kj && Rj.mode != 0) {
+        // the pair's own 2x2 block (Ri is Rj): the rotated diagonal, A_pq
+        // annihilated
+        if (Rj.mode == 1) {
+          d00 = make_double2(Rj.ap, 0.0);
+          d11 = make_double2(Rj.aq, 0.0);
         }
         d01 = make_double2(0.0, 0.0);
         d10 = d01;
@@ -1085,27 +1085,41 @@ __device__ __forceinline__ bool chol_inv(double2 *A, double2 *X, double *inv, in
 }
 
 // chol_inv on one wave for the 16 x 16 LDS matrices (ld 16), n <= 16: lane
-// l handles entries l + 64 u (u < 4), row (l >> 4) + 4 u, column l & 15.
-// Every step issues all its LDS reads unconditionally and selects the new
-// values branch-free, then writes; the wave's LDS accesses are performed in
-// program order, and wavefront-scope fences keep the compiler from moving
-// them across the read / write split.  Call from all 64 lanes of one wave;
-// the result is uniform.
-__device__ __forceinline__ bool chol_inv_wave16(double2 *A, double2 *X, double *inv, int n,
+// l holds entries l + 64 u (u < 4) in registers, row (l >> 4) + 4 u, column
+// l & 15.  A step exchanges one column (and, in the substitution, one row)
+// through a 32-entry LDS buffer -- one LDS round trip per step, all other
+// arithmetic in registers.  The new values are selected branch-free.  The
+// wave's LDS accesses are performed in program order, and wavefront-scope
+// fences keep the compiler from moving them across the write / read split.
+// A is left as it was (the factor stays in registers); X receives L^-1.
+// Call from all 64 lanes of one wave; the result is uniform.
+// c ? a : b per component (a conditional on the struct itself is lowered
+// through private memory)
+__device__ __forceinline__ double2 sel2(bool c, double2 a, double2 b) {
+  return make_double2(c ? a.x : b.x, c ? a.y : b.y);
+}
+__device__ __forceinline__ bool chol_inv_wave16(const double2 *A, double2 *X, double *inv, int n,
                                                 double dmax) {
+  __shared__ double2 xch[32];  // [0, 16): a column of L; [16, 32): a row of X
   const int l = threadIdx.x & 63, r0 = l >> 4, k = l & 15;
-  for (int j = 0; j < n; ++j) {
-    const double d = A[j * 17].x;
-    double2 a[4], aij[4];
+  double2 a[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = A[l + 64 * u];
-      aij[u] = A[(r0 + 4 * u) * 16 + j];
+  for (int u = 0; u < 4; ++u) a[u] = A[l + 64 * u];
+  for (int j = 0; j < n; ++j) {
+    // column j of the updated matrix, from the lanes of column j
+    if (k == j) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xch[r0 + 4 * u] = a[u];
     }
-    const double2 akj = A[k * 16 + j];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const double d = xch[j].x;
+    double2 aij[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) aij[u] = xch[r0 + 4 * u];
+    const double2 akj = xch[k];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (!(d > kCholPivot * dmax)) return false;
     const double il = rsq_nr(d), rd = il * il;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = r0 + 4 * u;
@@ -1114,37 +1128,48 @@ __device__ __forceinline__ bool chol_inv_wave16(double2 *A, double2 *X, double *
       const double py = aij[u].y * akj.x - aij[u].x * akj.y;
       const double2 t = make_double2(fma(-px, rd, a[u].x), fma(-py, rd, a[u].y));
       // column j (i >= j): L_ij = A_ij / sqrt(d), L_jj = sqrt(d)
-      const double2 c = i == j ? make_double2(d * il, 0.0) : make_double2(a[u].x * il, a[u].y * il);
+      const double2 c = sel2(i == j, make_double2(d * il, 0.0), make_double2(a[u].x * il, a[u].y * il));
       const bool live = i < n && k <= i;
-      const double2 v = !live ? a[u] : (k > j ? t : (k == j ? c : a[u]));
-      A[l + 64 * u] = v;
+      a[u] = sel2(live && k > j, t, sel2(live && k == j, c, a[u]));
     }
     if (l == 0) inv[j] = il;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
-  // L X = I, X holding the identity: at step i row i of X is scaled by
+  // L X = I, X starting as the identity: at step i row i of X is scaled by
   // 1 / L_ii (the rows above it applied) and applied to the rows below
+  double2 x[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) x[u] = make_double2(r0 + 4 * u == k ? 1.0 : 0.0, 0.0);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   for (int i = 0; i < n; ++i) {
     const double il = inv[i];
-    double2 x[4], lk[4];
+    const int ui = i >> 2;
+    double2 xo = x[0];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      x[u] = X[l + 64 * u];
-      lk[u] = A[(r0 + 4 * u) * 16 + i];
+    for (int u = 1; u < 4; ++u) xo = sel2(u == ui, x[u], xo);
+    // row i of X (scaled) from the lanes of row group i & 3, column i of L
+    // from the lanes of column i
+    if (r0 == (i & 3)) xch[16 + k] = make_double2(xo.x * il, xo.y * il);
+    if (k == i) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xch[r0 + 4 * u] = a[u];
     }
-    const double2 xi = X[i * 16 + k];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const double2 xs = make_double2(xi.x * il, xi.y * il);
+    const double2 xs = xch[16 + k];
+    double2 lk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) lk[u] = xch[r0 + 4 * u];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int row = r0 + 4 * u;
       const double2 t = make_double2(x[u].x - (lk[u].x * xs.x - lk[u].y * xs.y),
                                      x[u].y - (lk[u].x * xs.y + lk[u].y * xs.x));
       const bool live = k <= i && row < n && row >= i;
-      X[l + 64 * u] = !live ? x[u] : (row == i ? xs : t);
+      x[u] = sel2(live, sel2(row == i, xs, t), x[u]);
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) X[l + 64 * u] = x[u];
   return true;
 }
 
