@@ -97,7 +97,7 @@ constexpr int kPolyRows = 16;      // frames per polynomial-spectrum group (MFMA
 constexpr int kAcorrLags = 256;    // lags d per autocorrelation workgroup
 constexpr int kAcorrRows = 256;    // rows m per autocorrelation workgroup (partial sums)
 __host__ __device__ inline int acorr_blocks(int M) { return (M + kAcorrRows - 1) / kAcorrRows; }
-constexpr int kRefineGroups = 4;   // FP64 recompute workgroups per frame
+constexpr int kRefineGroups = 8;   // FP64 recompute workgroups per frame
 constexpr int kMaxL = 64;          // max sketch width of Method 2 (l)
 constexpr int kMaxN = 256;         // max sketch width of Method 1 (p)
 constexpr int kMaxK = 64;          // max number of sources

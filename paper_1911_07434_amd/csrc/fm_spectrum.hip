@@ -39,26 +39,23 @@ constexpr int kRefAngles = 4;  // angles per wave
 constexpr int kRefK = 4;       // sources per pass over the channels
 constexpr int kRefU = 4;       // 64-channel blocks fetched together
 
-// FP64 denominators of kRefAngles angles (phase frequencies F) by one wave.
+// FP64 terms |c_k|^2 of kRefAngles angles (phase frequencies F) by one
+// wave, for the source groups g0, g0 + gs, ... (kRefK sources a group).
 // Each lane walks every 64th channel with an FP64 phasor recurrence,
 // restarted exactly every 4096 channels (at most 64 steps per exact start,
 // error ~1e-14), and reads U_s straight from memory, kRefU 64-channel blocks
 // at a time: the frame's waves share it through the caches, and no wave
-// waits for another.  The sources are
-// taken kRefK at a time, the angles all at once, so every U_s element loaded
-// serves kRefAngles angles.
-__device__ void den_fp64_wave(const FrameDev &f, const unsigned long long (&F)[kRefAngles],
-                              int lane, double (&den)[kRefAngles]) {
+// waits for another.  The angles are taken all at once, so every U_s
+// element loaded serves kRefAngles angles.  term[k][j] receives |c_k|^2 of
+// angle j (written by lane 0).
+__device__ void proj_terms_wave(const FrameDev &f, const unsigned long long (&F)[kRefAngles],
+                                int lane, int g0, int gs, double (*term)[kRefAngles]) {
   const int M = f.M, K = f.K;
-  double proj[kRefAngles];
   double2 w[kRefAngles];
 #pragma unroll
-  for (int j = 0; j < kRefAngles; ++j) {
-    proj[j] = 0.0;
-    w[j] = phasor64(64, F[j]);
-  }
+  for (int j = 0; j < kRefAngles; ++j) w[j] = phasor64(64, F[j]);
   const int mlast = M - 1;
-  for (int k0 = 0; k0 < K; k0 += kRefK) {
+  for (int k0 = g0 * kRefK; k0 < K; k0 += gs * kRefK) {
     const int kn = min(kRefK, K - k0);
     const FM_GLOBAL double2 *u0 = (const FM_GLOBAL double2 *)(f.Us + (size_t)k0 * M);
     // rows past the last source repeat it; their sums are dropped below
@@ -118,27 +115,37 @@ __device__ void den_fp64_wave(const FrameDev &f, const unsigned long long (&F)[k
           re += __shfl_xor(re, o);
           im += __shfl_xor(im, o);
         }
-        if (k < kn) proj[j] += re * re + im * im;
+        if (k < kn && lane == 0) term[k0 + k][j] = re * re + im * im;
       }
   }
-#pragma unroll
-  for (int j = 0; j < kRefAngles; ++j) den[j] = (double)M - proj[j];
 }
 
-// FP64 recompute of the listed angles: kRefAngles consecutive list entries
-// per wave, the frame's kRefineGroups workgroups of four waves striding over
-// its list
+// FP64 recompute of the listed angles: each angle set (kRefAngles
+// consecutive list entries) takes min(G, 4) waves of a workgroup, G =
+// ceil(K / kRefK) source groups, the waves sharing out the groups; the
+// terms |c_k|^2 meet in LDS and one wave adds them in source order (the
+// order of the sum over k is that of a single wave's, whatever the split).
+// The frame's kRefineGroups workgroups stride over its list.
 template <bool kBatched>
 __global__ __launch_bounds__(256) void refine_kernel(FrameDev single, const FrameDev *frames,
                                                      const Item *items) {
   int part;
   const FrameDev &f = spec_frame<kBatched>(single, frames, items, part);
+  __shared__ double term[4][kMaxK][kRefAngles];
   const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const FM_GLOBAL int *rl = (const FM_GLOBAL int *)f.rlist;
   const int cnt = rl[0];
+  const int K = f.K;
   const double floor64 = (double)f.M * 1.1102230246251565e-16;  // M * 2^-53
-  const int stride = kRefineGroups * 4 * kRefAngles;
-  for (int e0 = (part * 4 + (threadIdx.x >> 6)) * kRefAngles; e0 < cnt; e0 += stride) {
+  const int ngrp = (K + kRefK - 1) / kRefK;
+  const int wps = min(ngrp, 4);          // waves per angle set
+  const int sets = 4 / wps;              // angle sets per workgroup step
+  const int set = wave / wps, g0 = wave % wps;
+  const bool active = set < sets;
+  const int stride = kRefineGroups * sets * kRefAngles;
+  for (int e00 = part * sets * kRefAngles; e00 < cnt; e00 += stride) {
+    const int e0 = e00 + set * kRefAngles;
     unsigned long long F[kRefAngles];
     int gl[kRefAngles];
     // entries past the end repeat the last one (computed, never stored)
@@ -150,13 +157,18 @@ __global__ __launch_bounds__(256) void refine_kernel(FrameDev single, const Fram
       gl[j] = e0 + j < cnt ? r[j] : -1;
       F[j] = turn_freq(f.theta0, f.dtheta, r[j]);
     }
-    double d[kRefAngles];
-    den_fp64_wave(f, F, lane, d);
-    if (lane == 0) {
+    if (active && e0 < cnt) proj_terms_wave(f, F, lane, g0, wps, term[set]);
+    __syncthreads();
+    if (active && g0 == 0 && e0 < cnt && lane < kRefAngles) {
+      double proj = 0.0;
+      for (int k = 0; k < K; ++k) proj += term[set][k][lane];
+      const double d = (double)f.M - proj;
+      int g = gl[0];
 #pragma unroll
-      for (int j = 0; j < kRefAngles; ++j)
-        if (gl[j] >= 0) f.P[gl[j]] = (float)(1.0 / fmax(d[j], floor64));
+      for (int j = 1; j < kRefAngles; ++j) g = lane == j ? gl[j] : g;
+      if (g >= 0) f.P[g] = (float)(1.0 / fmax(d, floor64));
     }
+    __syncthreads();
   }
 }
 
