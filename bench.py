@@ -428,9 +428,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="time only the main step (for profiler runs); same as --legs ''")
-    ap.add_argument("--legs", default="compare,large,uneven,serve",
+    ap.add_argument("--legs", default="compare,alone,large,uneven,serve",
                     help="extra legs after the main step: compare (mixed precision, Method 1, "
-                         "standard MUSIC, latency alone), large (M=4096 T=8192 frames at "
+                         "standard MUSIC), alone (one frame's latency), large (M=4096 T=8192 frames at "
                          "every precision), uneven (512-frame uneven batch), serve (Poisson "
                          "serving trace)")
     ap.add_argument("--prec", choices=("fp32", "fp16", "bf16", "fp16x3", "bf16x3"),
@@ -781,6 +781,15 @@ def main():
             vplain = nb * reps / (time.perf_counter() - t0)
         log(f"plain MUSIC (rocSOLVER eigh): {vplain:.2f} frames/s")
 
+        out["comparison"] = {
+            "method1_frames_per_s": round(v1, 2),
+            "plain_music_frames_per_s": round(vplain, 3),
+            "plain_music_eig": "torch.linalg.eigh (rocSOLVER), complex64",
+            "speedup_method2_vs_plain": round(value / vplain, 1),
+            "speedup_method1_vs_plain": round(v1 / vplain, 1),
+        }
+
+    if "alone" in legs:
         # ---- one frame alone: latency distribution -------------------------
         # (stage by stage with events between the stages, and the whole frame
         # as one graph replay; FP32 path, then the mixed path)
@@ -812,13 +821,6 @@ def main():
                                      for j, n in enumerate(stage_names)},
                     "graph_replay_p50": round(float(np.percentile(lat_g, 50)), 3),
                     "graph_replay_p99": round(float(np.percentile(lat_g, 99)), 3)}
-        out["comparison"] = {
-            "method1_frames_per_s": round(v1, 2),
-            "plain_music_frames_per_s": round(vplain, 3),
-            "plain_music_eig": "torch.linalg.eigh (rocSOLVER), complex64",
-            "speedup_method2_vs_plain": round(value / vplain, 1),
-            "speedup_method1_vs_plain": round(v1 / vplain, 1),
-        }
         out["frame_latency_ms_alone"] = alone(fm.FM_FP32)
         out["frame_latency_ms_alone"]["fp16"] = alone(fm.FM_FP16)
         log(f"one frame alone: {out['frame_latency_ms_alone']}")
