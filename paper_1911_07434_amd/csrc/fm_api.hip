@@ -1209,12 +1209,14 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     if (frames[i].esprit_deg) items.push_back({i, 0, 0, 0});
   add(p->sub, kEsprit, 0, 0, b0);
 
-  // spectrum (every precision): reset the recompute lists, lag sums of
-  // every frame into its group buffer (row-block partials, then their sums
-  // per group), then each group's polynomial pass (tiles of the knob's width
-  // for the group's bucket)
+  // spectrum (every precision): reset the recompute lists (the lag-sum
+  // kernel resets those of its frames), lag sums of every frame into its
+  // group buffer (row-block partials, then their sums per group), then each
+  // group's polynomial pass (tiles of the knob's width for the group's
+  // bucket)
   b0 = begin();
-  for (int i : order) items.push_back({i, 0, 0, 0});
+  for (int i : order)
+    if (grp_of[i] < 0) items.push_back({i, 0, 0, 0});
   add(p->spec, kSpecPrep, 0, 0, b0);
   // one lag per lane (four times the workgroups, the same bits) when the
   // plan's lag-sum workgroups would be few

@@ -83,6 +83,9 @@ __global__ __launch_bounds__(kAcThreads) void acorr_kernel(FrameDev single,
     fp = &single;
   }
   const int M = fp->M, K = fp->K;
+  // the first workgroup of a frame empties its FP64-recompute list, which
+  // the polynomial pass fills next (the previous run's readers are done)
+  if (chunk == 0 && rb == 0 && threadIdx.x == 0) fp->rlist[0] = 0;
   const double2 *Us = fp->Us;
   FM_GLOBAL float2 *hg = (FM_GLOBAL float2 *)(fp->hgrp + (size_t)rb * M * kPolyRows);
   const int slot = fp->hslot;

@@ -942,19 +942,23 @@ __device__ __forceinline__ int jacobi_wave16(double2 *A, double2 *V) {
     }
     if (off == 0.0 || off <= 1e-30 * tot) return sweep;
     if (sweep == kMaxSweeps) return -1;
+    // the round's pairs (pi < qi of pair ki, pj < qj of pair kj); those of
+    // the next round are formed during this one (integer work off the
+    // round's chain of LDS reads and FP64 operations)
+    auto pairs = [&](int round, int &pi, int &qi, int &pj, int &qj) {
+      pi = rr16(ki, round);
+      qi = rr16(15 - ki, round);
+      pj = rr16(kj, round);
+      qj = rr16(15 - kj, round);
+      const int ti = min(pi, qi), tj = min(pj, qj);
+      qi = max(pi, qi);
+      pi = ti;
+      qj = max(pj, qj);
+      pj = tj;
+    };
+    int pi, qi, pj, qj;
+    pairs(0, pi, qi, pj, qj);
     for (int round = 0; round < 15; ++round) {
-      int pi = rr16(ki, round), qi = rr16(15 - ki, round);
-      int pj = rr16(kj, round), qj = rr16(15 - kj, round);
-      if (pi > qi) {
-        const int t = pi;
-        pi = qi;
-        qi = t;
-      }
-      if (pj > qj) {
-        const int t = pj;
-        pj = qj;
-        qj = t;
-      }
       const double apj = A[pj * 17].x, aqj = A[qj * 17].x;
       const double2 bj = A[pj * 16 + qj];
       const double2 b00 = A[pi * 16 + pj], b01 = A[pi * 16 + qj];
@@ -962,6 +966,8 @@ __device__ __forceinline__ int jacobi_wave16(double2 *A, double2 *V) {
       const double2 vp0 = V[ki * 16 + pj], vq0 = V[ki * 16 + qj];
       const double2 vp1 = V[(ki + 8) * 16 + pj], vq1 = V[(ki + 8) * 16 + qj];
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      int npi, nqi, npj, nqj;
+      pairs(round + 1 < 15 ? round + 1 : 0, npi, nqi, npj, nqj);
       const RotW Rj = make_rot(apj, aqj, bj);
       // pair ki's rotation: lane ki computed it as its pair kj
       RotW Ri;
@@ -1009,6 +1015,10 @@ __device__ __forceinline__ int jacobi_wave16(double2 *A, double2 *V) {
       V[(ki + 8) * 16 + pj] = colp(vp1, vq1);
       V[(ki + 8) * 16 + qj] = colq(vp1, vq1);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      pi = npi;
+      qi = nqi;
+      pj = npj;
+      qj = nqj;
     }
   }
 }

@@ -893,3 +893,37 @@ def test_plan_rejects_bf16_spectrum_pass(ctx):
     with pytest.raises(fm.FmError) as e:
         fm.Plan(ctx, [d.descriptor()])
     assert e.value.status == fm.FM_E_UNSUPPORTED
+
+
+# ----------------------------------------------------------------------------
+# the batch forms of every stage against the one-frame forms, bitwise: a plan
+# of 64 frames (M = 1024) runs the covariance and sketch products without
+# channel segments in separate workgroups, the four-lag form of the lag sums
+# and 256-angle polynomial tiles; a plan of one of its frames runs segment
+# workgroups with in-order reductions, one lag per lane and 64-angle tiles
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", [fm.FM_FP32, fm.FM_FP16])
+def test_plan_forms_batch_equals_one_frame_bitwise(ctx, prec):
+    M, T, K, B, L = 1024, 256, 8, 64, 18001
+    X, _ = fmsynth.make_batch_device(M, T, K, 0.0, B, 31)
+    Om = fmsynth.make_omega_device(M, 16, B, 31)
+    th0, dth, _ = fmsynth.grid(L)
+    spec = FrameSpec(M=M, T=T, K=K, method=fm.FM_METHOD_PROJECT, n=16, q=2, L=L,
+                     theta0_deg=th0, dtheta_deg=dth)
+    assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 0) == 256  # the built-in wide tile
+    devs = [DeviceFrame(spec, X=X[i], rnd=Om[i]) for i in range(B)]
+    plan = fm.Plan(ctx, [d.descriptor() for d in devs], prec=prec)
+    plan.run()
+    torch.cuda.synchronize()
+    plan.close()
+    for i in (0, 37, B - 1):
+        one = DeviceFrame(spec, X=X[i], rnd=Om[i])
+        p1 = fm.Plan(ctx, [one.descriptor()], prec=prec)
+        p1.run()
+        torch.cuda.synchronize()
+        p1.close()
+        a, b = devs[i].results(), one.results()
+        for key in ("R", "Us", "sigma", "P", "peak_idx"):
+            assert np.array_equal(a[key], b[key]), (i, key)
+        assert a["status"] == b["status"] == 0
