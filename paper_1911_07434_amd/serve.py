@@ -205,15 +205,21 @@ class ServeStats:
 
 class Server:
     """Continuous batching: admission by memory budget, FIFO batches, one
-    batch in flight per stream, streams overlapping on the device."""
+    batch in flight per stream, streams overlapping on the device.
+
+    max_batch_cost (optional, in the units of the executor's frame_cost):
+    a batch stops growing before its estimated work would pass the cap (its
+    first frame is always taken), so that batches stay short when a burst
+    of large frames arrives and the streams keep finishing work often."""
 
     def __init__(self, executor, budget_bytes: int, n_streams: int = 2, max_batch: int = 64,
-                 clock=None, stall_timeout_s: float = 30.0):
+                 clock=None, stall_timeout_s: float = 30.0, max_batch_cost: float | None = None):
         assert n_streams >= 1
         self.ex = executor
         self.pool = PoolAllocator(budget_bytes)
         self.n_streams = n_streams
         self.max_batch = max_batch
+        self.max_batch_cost = max_batch_cost
         self.clock = clock or WallClock()
         self.stall_timeout_s = stall_timeout_s
 
@@ -226,8 +232,13 @@ class Server:
         """Take queued requests FIFO while their frame memory fits the budget;
         the head of the queue is never overtaken."""
         taken = []
+        cost = 0.0
         while queue and len(taken) < self.max_batch:
             req = queue[0]
+            if self.max_batch_cost is not None:
+                c = self.ex.frame_cost(req)
+                if taken and cost + c > self.max_batch_cost:
+                    break
             need = self.ex.frame_bytes(req)
             if need > self.pool.size:
                 queue.popleft()
@@ -240,6 +251,8 @@ class Server:
             req.mem = (off, need)
             req.admitted = now
             taken.append(req)
+            if self.max_batch_cost is not None:
+                cost += c
         if not taken:
             return None
         pbytes = self.ex.plan_bytes(taken)
@@ -455,6 +468,18 @@ class GpuExecutor:
 
     def frame_bytes(self, req) -> int:
         return self._layout(req)[1]
+
+    # sustained rates of the covariance and of the sketch products (flop/s),
+    # measured at M = 1024; the cost is a batching estimate, not a bound
+    _RATES = {0: (1.4e14, 1.0e14), 1: (6.5e14, 1.0e14)}
+
+    def frame_cost(self, req) -> float:
+        """Estimated device seconds of one frame: covariance 4 M^2 T flops,
+        sketch products 8 M^2 l (q + 1), a fixed 50 us for the rest."""
+        cov_rate, sk_rate = self._RATES[0 if self.prec == 0 else 1]
+        M = float(req.M)
+        return (4.0 * M * M * req.T / cov_rate + 8.0 * M * M * max(req.n, 1) * (req.q + 1) / sk_rate
+                + 5e-5)
 
     def _descriptor(self, req):
         d = getattr(req, "_desc", None)

@@ -25,6 +25,9 @@ class FakeExecutor:
     def frame_bytes(self, req):
         return req.M * req.M * 8
 
+    def frame_cost(self, req):
+        return self.per_frame_s * (req.M / 1024) ** 2 * req.T / 2048
+
     def plan_bytes(self, reqs):
         return self._plan_bytes * len(reqs)
 
@@ -196,3 +199,30 @@ def test_budget_binding_run_reports_admission_waits():
     # binding the budget delays admission relative to an unbounded run
     assert np.percentile(st.admission_wait_ms, 99) > np.percentile(free.admission_wait_ms, 99)
     assert srv.pool.used == 0
+
+
+def test_batch_cost_cap_keeps_batches_short_and_fifo():
+    # a burst of mixed frames: with the cap, a batch stops growing before its
+    # estimated work passes it (a frame over the cap runs alone), the launch
+    # order stays the arrival order, and every frame completes
+    clk = VirtualClock()
+    ex = FakeExecutor(clk, per_frame_s=1e-3)
+    rng = np.random.default_rng(3)
+    reqs = [Request(rid=i, arrival=1e-5 * i, M=int(rng.choice([256, 1024, 4096])),
+                    T=int(rng.integers(64, 4097)), K=4, n=12) for i in range(300)]
+    cap = 4e-3
+    st = Server(ex, budget_bytes=1 << 40, n_streams=3, max_batch=64, clock=clk,
+                max_batch_cost=cap).run(reqs)
+    assert st.completed == 300
+    by_id = {r.rid: r for r in reqs}
+    for _, _, rids in ex.launches:
+        if len(rids) > 1:
+            assert sum(ex.frame_cost(by_id[i]) for i in rids) <= cap + 1e-12
+    order = [rid for _, _, rids in sorted(ex.launches, key=lambda x: x[0]) for rid in rids]
+    assert order == sorted(order)
+    # without the cap the same burst forms longer batches
+    clk2 = VirtualClock()
+    ex2 = FakeExecutor(clk2, per_frame_s=1e-3)
+    reqs2 = [Request(rid=r.rid, arrival=r.arrival, M=r.M, T=r.T, K=4, n=12) for r in reqs]
+    Server(ex2, budget_bytes=1 << 40, n_streams=3, max_batch=64, clock=clk2).run(reqs2)
+    assert max(len(r) for _, _, r in ex2.launches) > max(len(r) for _, _, r in ex.launches)
