@@ -10,8 +10,10 @@
 // (fm_spectrum16.hip).  Both append every angle whose denominator is below
 // M/16 (the cancellation-prone main lobes) to a per-frame list, and the
 // refine kernel here recomputes those angles in FP64 from the FP64 U_s (four
-// angles per wave); a denominator below M*2^-53 is clamped there (noiseless
-// on-grid pole).  Also here: the list reset of a plan and the transposed
+// angles per set, a set's sources shared out over up to four waves); a
+// denominator below M*2^-53 is clamped there (noiseless on-grid pole).  Also
+// here: the list reset of a plan's frames on the FP16 projection pass (the
+// lag-sum kernel resets those of the polynomial pass) and the transposed
 // FP32 copy of U_s of a single-frame call.
 #include "fm_internal.h"
 #include "fm_steer.h"
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(256) void refine_kernel(FrameDev single, const Fram
   }
 }
 
-// reset the recompute lists of the frames of a plan
+// reset the recompute lists of a plan's frames on the FP16 projection pass
 __global__ void spec_prep_kernel(const FrameDev *frames, const Item *items, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) frames[items[i].frame].rlist[0] = 0;
