@@ -185,7 +185,11 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int m = 4 * (s >> 1) + 2 * h + (s & 1);
-        const float2 v = okc[b] ? vb[m * n + col[b]] : make_float2(0.f, 0.f);
+        // unconditional read (col is 0 for an unused block), then a select:
+        // a conditional read would branch around every MFMA pair and wait
+        // for its own LDS read
+        const float2 v0 = vb[m * n + col[b]];
+        const float2 v = make_float2(okc[b] ? v0.x : 0.f, okc[b] ? v0.y : 0.f);
         const float bre = part[b] == 0 ? v.x : v.y;
         const float bim = part[b] == 0 ? -v.y : v.x;
         acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s].x, bre, acc[b], 0, 0, 0);
@@ -445,7 +449,8 @@ __device__ __forceinline__ void xhv_cols(const FrameDev &f, int t0w,
     for (int s = 0; s < kSteps; ++s) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const float2 v = okc[b] ? vb[(2 * s + h) * n + col[b]] : make_float2(0.f, 0.f);
+        const float2 v0 = vb[(2 * s + h) * n + col[b]];  // unconditional, as in sketch_rows
+        const float2 v = make_float2(okc[b] ? v0.x : 0.f, okc[b] ? v0.y : 0.f);
         const float b1 = part[b] == 0 ? v.x : v.y;    // with Xr
         const float b2 = part[b] == 0 ? v.y : -v.x;   // with Xi
         acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s].x, b1, acc[b], 0, 0, 0);
