@@ -313,7 +313,9 @@ hipError_t run_project_single(FrameDev &f, hipStream_t s, fm_prec prec) {
     if ((r = fm::launch_small(f, nullptr, nullptr, 0, fm::kOrth, s)) != hipSuccess) return r;
     return fm::launch_apply(f, nullptr, nullptr, 0, fm::kApplyV, s);
   };
-  if ((e = fm::launch_omega(f, nullptr, nullptr, 0, 0, s)) != hipSuccess) return e;
+  // (with power iterations the first product reads Omega itself)
+  if ((from_x || f.q == 0) && (e = fm::launch_omega(f, nullptr, nullptr, 0, 0, s)) != hipSuccess)
+    return e;
   if (f.q == 0 && (e = orth(false)) != hipSuccess) return e;
   for (int r = 0; r <= f.q; ++r) {
     if (r > 0 && (e = orth(true)) != hipSuccess) return e;
@@ -1076,13 +1078,15 @@ static fm_status plan_build(fm_ctx *ctx, const fm_frame *frames, int n_frames, f
     add(p->cov, kCov, 0, 0, b0);
   }
 
-  // stage 2 init: Omega -> V / Y (Method 2), gather (Method 1)
+  // stage 2 init: Omega -> V / Y (Method 2 without power iterations, or
+  // without R; the first product with R reads Omega itself), gather
+  // (Method 1)
   b0 = begin();
   auto is_proj = [&](int i) {
     return frames[i].method == FM_METHOD_PROJECT || frames[i].method == FM_METHOD_PROJECT_X;
   };
   for (int i : order)
-    if (is_proj(i))
+    if (is_proj(i) && (frames[i].method == FM_METHOD_PROJECT_X || frames[i].q == 0))
       for (int c = 0; c < rows(frames[i].M, fm::kApplyRows); ++c) items.push_back({i, c, 0, 0});
   add(p->sub, kOmega, 0, 0, b0);
   b0 = begin();

@@ -86,6 +86,12 @@ struct Item {
 
 constexpr int kGramRows = 128;     // rows of the sketch per Gram partial
 constexpr int kSmallSlots = 8;     // npad^2 complex128 matrices per frame
+// the frame's workspace status word, after the small dense slots: cleared
+// by the first launch of the subspace step, or-ed by the orth steps, read
+// by the final small solve
+__device__ inline unsigned *wstat_of(const FrameDev &f) {
+  return reinterpret_cast<unsigned *>(f.small + (size_t)kSmallSlots * f.npad * f.npad);
+}
 constexpr int kCovTile = 128;      // 16-bit covariance: tile edge (complex entries)
 constexpr int kCovBlock = 64;      // FP32 covariance: rows of a wave block (one wave per block)
 constexpr int kCovPartFloats = 64 * 64;  // FP32 covariance: one segment's sums of a wave block

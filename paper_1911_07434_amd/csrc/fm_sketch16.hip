@@ -111,12 +111,20 @@ __global__ __launch_bounds__(256) void sketch16_kernel(FrameDev single, const Fr
   f32x2 vreg[JB];
   // (global-address-space loads: a flat load's wait would also wait for the
   // R prefetch and the LDS traffic)
+  // The first product of a power iteration (round 0, q > 0) multiplies the
+  // real test matrix, read as such (zero imaginary parts); that launch also
+  // clears the frame's workspace status word, which the orth steps may set.
   const gf32x2 *Vg = (const gf32x2 *)V;
+  const FM_GLOBAL float *Vr = orth_v ? nullptr : (const FM_GLOBAL float *)f.Omega;
+  if (!orth_v && blk == 0 && seg == 0 && tid == 0 && split != 2) *wstat_of(f) = 0u;
   auto load_b = [&](int c, int lim) {
 #pragma unroll
     for (int j = 0; j < JB; ++j) {
       const int e = min(tid + 256 * j, lim - 1);
-      vreg[j] = Vg[(size_t)c * kCh * n + e];
+      if (Vr)
+        vreg[j] = f32x2{Vr[(size_t)c * kCh * n + e], 0.f};
+      else
+        vreg[j] = Vg[(size_t)c * kCh * n + e];
     }
   };
   auto store_b = [&](int buf, int lim) {

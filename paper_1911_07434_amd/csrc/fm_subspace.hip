@@ -52,9 +52,6 @@ __device__ __forceinline__ const FrameDev &frame_of(const FrameDev &single,
   }
 }
 
-__device__ inline unsigned *wstat_of(const FrameDev &f) {
-  return reinterpret_cast<unsigned *>(f.small + (size_t)kSmallSlots * f.npad * f.npad);
-}
 __device__ inline double2 *slot(const FrameDev &f, int s) {
   return f.small + (size_t)s * f.npad * f.npad;
 }
@@ -123,7 +120,8 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
                                             const float2 *Am, long long lda, int kdim,
                                             const float2 *Bm, float scale,
                                             float2 (*vbuf)[kSkChunkMax * kMaxL],
-                                            int segs = 1, int split = 0, int seg = 0) {
+                                            int segs = 1, int split = 0, int seg = 0,
+                                            const float *Breal = nullptr) {
   constexpr int kSkChunk = 2 * SK;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -161,11 +159,17 @@ __device__ __forceinline__ void sketch_rows(const FrameDev &f, int i0, int chunk
   float2 vst[JV];
   // V rows of chunk c (kSkChunk x n, row-major); elements past `lim` (rows
   // past kdim) are read from a valid address and replaced by zero on store
+  // (Breal: B is real, given as its [kdim][n] values -- the Gaussian test
+  // matrix of the first product -- and enters with zero imaginary parts)
+  const FM_GLOBAL float *Vr = (const FM_GLOBAL float *)Breal;
   auto load_v = [&](int c, int lim) {
 #pragma unroll
     for (int j = 0; j < JV; ++j) {
       const int e = min(tid + 256 * j, lim - 1);
-      vst[j] = V[(size_t)c * kSkChunk * n + e];
+      if (Vr)
+        vst[j] = make_float2(Vr[(size_t)c * kSkChunk * n + e], 0.f);
+      else
+        vst[j] = V[(size_t)c * kSkChunk * n + e];
     }
   };
   auto store_v = [&](int buf, int lim) {
@@ -371,8 +375,14 @@ __global__ __launch_bounds__(256) void sketch_kernel(FrameDev single, const Fram
   // rows start past M clamp to row M-1 and store nothing
   const int i0 = blk * kSketchRows + (threadIdx.x >> 6) * 32;
   const int gmode = round < 0 ? -1 : (round < f.q ? kGramSelf : kGramFinal);
+  // the first product of a power iteration multiplies the test matrix itself
+  // (read here as real values) and clears the frame's workspace status word,
+  // which the orth steps that follow may set
+  const bool first = round == 0 && f.q > 0;
+  if (first && blk == 0 && seg == 0 && threadIdx.x == 0 && split != 2) *wstat_of(f) = 0u;
   sketch_rows<NB, (NB <= 2 ? 16 : 8)>(f, i0, blk, gmode, f.R, f.ldr, f.M, f.V, 1.f, vbuf,
-                                      sketch_segments(f.M, NB), split, seg);
+                                      sketch_segments(f.M, NB), split, seg,
+                                      first ? f.Omega : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1576,10 +1586,11 @@ hipError_t launch_sketch(const FrameDev &single, const FrameDev *frames, const I
                          int n_items, int nb, int round, int split, hipStream_t s) {
   const int S = split == 1 ? sketch_segments(single.M, nb) : 1;
   const dim3 g(items ? n_items : S * ((single.M + kSketchRows - 1) / kSketchRows)), b(256);
-  const int rd = nb <= 2 ? round : -1;
-#define FM_SK(NB)                                                                                        \
-  if (items) hipLaunchKernelGGL((sketch_kernel<NB, true>), g, b, 0, s, single, frames, items, rd, split); \
-  else hipLaunchKernelGGL((sketch_kernel<NB, false>), g, b, 0, s, single, frames, items, rd, split);
+  // (every class gets the round: the first product reads the test matrix;
+  // only the classes n <= 32 form Gram partials with it)
+#define FM_SK(NB)                                                                                           \
+  if (items) hipLaunchKernelGGL((sketch_kernel<NB, true>), g, b, 0, s, single, frames, items, round, split); \
+  else hipLaunchKernelGGL((sketch_kernel<NB, false>), g, b, 0, s, single, frames, items, round, split);
   switch (nb) {
     case 1: FM_SK(1); break;
     case 2: FM_SK(2); break;
