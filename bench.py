@@ -801,13 +801,13 @@ def main():
                     step(plan_one)
                     plan_one.run(use_graph=True, stream=stream)
                 torch.cuda.synchronize()
-                for i in range(40):
+                for i in range(200):
                     ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
                     step(plan_one, ev)
                     ev[4].synchronize()
                     lat.append(ev[0].elapsed_time(ev[4]))
                     st.append([ev[j].elapsed_time(ev[j + 1]) for j in range(4)])
-                for i in range(40):
+                for i in range(200):
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record(stream)
                     plan_one.run(use_graph=True, stream=stream)
