@@ -453,6 +453,9 @@ class GpuExecutor:
         key = (M, l)
         if key not in self.omega:
             self.omega[key] = self.fmsynth.make_omega_device(M, l, 1, 1000 * M + l)[0].contiguous()
+            # drawn on the current stream, read by batches on the executor's
+            # streams (which do not wait for it): complete it first
+            self.torch.cuda.current_stream().synchronize()
         return self.omega[key]
 
     @staticmethod

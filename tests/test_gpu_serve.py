@@ -36,14 +36,17 @@ def _unpack(raw, lay, req):
                 pidx=take("pidx", np.int32, K))
 
 
-def test_served_frames_equal_alone_bitwise(ctx):
+@pytest.mark.parametrize("max_batch_cost", [None, 2e-4])
+def test_served_frames_equal_alone_bitwise(ctx, max_batch_cost):
+    # (with the cost cap, batches of these small frames hold up to three)
     Ms = (128, 256, 512)
     reqs = poisson_arrivals(20000.0, 10.0, seed=3, Ms=Ms, T_range=(64, 512), K_range=(1, 12),
                             L=2001, max_frames=48)
     ex = GpuExecutor(ctx, pool_bytes=1 << 30, n_streams=3, keep_results=True)
     clock = WallClock()
     ex.start(clock)
-    st = Server(ex, budget_bytes=1 << 30, n_streams=3, max_batch=8, clock=clock).run(reqs)
+    st = Server(ex, budget_bytes=1 << 30, n_streams=3, max_batch=8, clock=clock,
+                max_batch_cost=max_batch_cost).run(reqs)
     torch.cuda.synchronize()
     assert st.completed == len(reqs) and st.failed == 0
     assert st.batches < len(reqs)            # frames were batched together
