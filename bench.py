@@ -256,7 +256,7 @@ def uneven_leg(fm, torch, stream, seed, steps, tune_cache=None):
         base = timed(plan, steps)
         ref = [frames[i].P.cpu().numpy() for i in range(0, 512, 37)]
         plan.close()
-        table = autotune.tune(c, frames, prec, reps=3, max_frames=64, stream=stream, log=log)
+        table = autotune.tune(c, frames, prec, reps=3, max_frames=512, stream=stream, log=log)
         if tune_cache:
             key = autotune.cache_key(torch.cuda.get_device_name(0), autotune.library_id(), prec)
             autotune.save(tune_cache, key, table)

@@ -52,13 +52,15 @@ bool knob_value_ok(int knob, int bucket, int v) {
   return v == 64 || v == 128 || (v == 256 && bucket < 4);
 }
 
-// built-in choices (measured on an MI355X at the 1024-channel shapes): a
-// wider angle tile reuses each generated phasor and staged operand for more
-// angles (in the FP16 pass until register pressure from the 2K stacked
-// outputs takes over); the best polynomial-pass tile depends on how full the
-// groups are, which the autotuner measures per batch
+// built-in choices (measured on an MI355X): a wider angle tile reuses each
+// generated phasor and staged operand for more angles (in the FP16 pass
+// until register pressure from the 2K stacked outputs takes over); the best
+// polynomial-pass tile depends on how full the groups are -- at full groups
+// of equal frames 64, 128 and 256 angles are within 2%, in a batch of mixed
+// K 256 is 5-12% slower than 128 -- which the autotuner measures per batch
 int knob_default(int knob, int bucket) {
   if (knob == FM_KNOB_COV_SCHEDULE) return 2;
+  if (knob == FM_KNOB_SPEC_ANGLES) return bucket < 6 ? 128 : 64;
   return bucket < 2 ? 256 : (bucket < 6 ? 128 : 64);
 }
 

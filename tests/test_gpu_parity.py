@@ -899,7 +899,7 @@ def test_plan_rejects_bf16_spectrum_pass(ctx):
 # the batch forms of every stage against the one-frame forms, bitwise: a plan
 # of 64 frames (M = 1024) runs the covariance and sketch products without
 # channel segments in separate workgroups, the four-lag form of the lag sums
-# and 256-angle polynomial tiles; a plan of one of its frames runs segment
+# and 128-angle polynomial tiles; a plan of one of its frames runs segment
 # workgroups with in-order reductions, one lag per lane and 64-angle tiles
 # ----------------------------------------------------------------------------
 
@@ -911,7 +911,7 @@ def test_plan_forms_batch_equals_one_frame_bitwise(ctx, prec):
     th0, dth, _ = fmsynth.grid(L)
     spec = FrameSpec(M=M, T=T, K=K, method=fm.FM_METHOD_PROJECT, n=16, q=2, L=L,
                      theta0_deg=th0, dtheta_deg=dth)
-    assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 0) == 256  # the built-in wide tile
+    assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 0) == 128  # the built-in tile (wider than 64)
     devs = [DeviceFrame(spec, X=X[i], rnd=Om[i]) for i in range(B)]
     plan = fm.Plan(ctx, [d.descriptor() for d in devs], prec=prec)
     plan.run()

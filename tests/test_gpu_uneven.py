@@ -71,6 +71,7 @@ def _same(a, b):
 
 def test_knob_defaults_and_validation(ctx):
     assert ctx.get_knob(fm.FM_KNOB_COV_SCHEDULE, 0) == 2        # per-precision built-in
+    assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 0) == 128
     assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 3) == 128
     assert ctx.get_knob(fm.FM_KNOB_SPEC_ANGLES, 7) == 64
     assert ctx.get_knob(fm.FM_KNOB_SPEC16_ANGLES, 0) == 256
