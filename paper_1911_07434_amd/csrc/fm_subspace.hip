@@ -1548,8 +1548,11 @@ __global__ __launch_bounds__(256) void apply_kernel(FrameDev single, const Frame
       ys[j * kApplyRows + m] = Yg[(size_t)(m0 + m) * n + j];
     }
     __syncthreads();
+    // V ([M][n]) is written with the column fastest across a wave (whole
+    // rows: coalesced), U_s ([K][M]) with the row fastest
+    const bool cfast = mode == kApplyV;
     for (int e = threadIdx.x; e < rows * ncol; e += blockDim.x) {
-      const int c = e / rows, ml = e % rows;
+      const int c = cfast ? e % ncol : e / rows, ml = cfast ? e / ncol : e % rows;
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll 4
       for (int j = 0; j < n; ++j) mac(acc, ys[j * kApplyRows + ml], ts[j * ncol + c]);
